@@ -1,0 +1,303 @@
+/*
+ * FP64 CPU oracle for FastMDP first-come-first-served pre-departure planning.
+ * TEST INFRASTRUCTURE ONLY -- see fastmdp_oracle.h for scope and readings.
+ *
+ * Written to be checked against the paper by eye: every per-peak term is
+ * evaluated literally (one distance, one radius test and one discount power
+ * per peak, then a maximum), in the order of the paper's algorithms.  No
+ * blocking, no min-distance shortcut, no reuse across actions.
+ */
+#include "fastmdp_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t t0, n;
+    float *xyz;          /* n points, FP32 (the table's storage format) */
+} orc_plan_rec;
+
+struct orc_world {
+    orc_config cfg;
+    double ell;          /* metres per step at the fastest speed */
+    int32_t n_plans, cap_plans;
+    orc_plan_rec *plans;
+    int32_t tnx, tny;
+    float *terr;
+    double tx0, ty0, tcell;
+};
+
+static double max_speed(const orc_config *c) {
+    double m = 0.0;
+    for (int v = 0; v < c->n_speed; ++v)
+        if (c->speed[v] > m) m = c->speed[v];
+    return m;
+}
+
+int orc_create(const orc_config *cfg, orc_world **out) {
+    if (!cfg || !out) return ORC_E_INVAL;
+    if (cfg->n_head < 1 || cfg->n_climb < 1 || cfg->n_speed < 1 ||
+        cfg->n_climb > ORC_MAX_ACT_DIM || cfg->n_speed > ORC_MAX_ACT_DIM || cfg->dt <= 0.0)
+        return ORC_E_INVAL;
+    orc_world *w = (orc_world *)calloc(1, sizeof(orc_world));
+    if (!w) return ORC_E_NOMEM;
+    w->cfg = *cfg;
+    w->ell = max_speed(cfg) * cfg->dt;
+    if (!(w->ell > 0.0)) { free(w); return ORC_E_INVAL; }
+    *out = w;
+    return 0;
+}
+
+void orc_destroy(orc_world *w) {
+    if (!w) return;
+    for (int j = 0; j < w->n_plans; ++j) free(w->plans[j].xyz);
+    free(w->plans);
+    free(w->terr);
+    free(w);
+}
+
+int orc_num_plans(const orc_world *w) { return w ? w->n_plans : ORC_E_INVAL; }
+
+int orc_add_plan(orc_world *w, int32_t t0, int32_t n, const float *xyz) {
+    if (!w || n < 1 || t0 < 0 || !xyz) return ORC_E_INVAL;
+    if (w->n_plans == w->cap_plans) {
+        int32_t nc = w->cap_plans ? 2 * w->cap_plans : 64;
+        orc_plan_rec *p = (orc_plan_rec *)realloc(w->plans, (size_t)nc * sizeof(orc_plan_rec));
+        if (!p) return ORC_E_NOMEM;
+        w->plans = p;
+        w->cap_plans = nc;
+    }
+    float *copy = (float *)malloc((size_t)n * 3 * sizeof(float));
+    if (!copy) return ORC_E_NOMEM;
+    memcpy(copy, xyz, (size_t)n * 3 * sizeof(float));
+    w->plans[w->n_plans].t0 = t0;
+    w->plans[w->n_plans].n = n;
+    w->plans[w->n_plans].xyz = copy;
+    w->n_plans++;
+    return 0;
+}
+
+int orc_set_terrain(orc_world *w, int32_t nx, int32_t ny, const float *h,
+                    double x0, double y0, double cell) {
+    if (!w || nx < 2 || ny < 2 || !h || !(cell > 0.0)) return ORC_E_INVAL;
+    float *copy = (float *)malloc((size_t)nx * ny * sizeof(float));
+    if (!copy) return ORC_E_NOMEM;
+    memcpy(copy, h, (size_t)nx * ny * sizeof(float));
+    free(w->terr);
+    w->terr = copy;
+    w->tnx = nx; w->tny = ny; w->tx0 = x0; w->ty0 = y0; w->tcell = cell;
+    return 0;
+}
+
+/* Plan j's position at time row t, if it is active there. */
+static int plan_point(const orc_plan_rec *p, int32_t t, double q[3]) {
+    if (t < p->t0 || t >= p->t0 + p->n) return 0;
+    const float *x = p->xyz + (size_t)(t - p->t0) * 3;
+    q[0] = (double)x[0]; q[1] = (double)x[1]; q[2] = (double)x[2];
+    return 1;
+}
+
+static double dist3(const double a[3], const double b[3]) {
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* Terrain height: bilinear interpolation of the vertex grid, the position
+ * clamped to the grid's extent. */
+static double terrain_height(const orc_world *w, double x, double y) {
+    double fx = (x - w->tx0) / w->tcell;
+    double fy = (y - w->ty0) / w->tcell;
+    if (fx < 0.0) fx = 0.0;
+    if (fy < 0.0) fy = 0.0;
+    if (fx > (double)(w->tnx - 1)) fx = (double)(w->tnx - 1);
+    if (fy > (double)(w->tny - 1)) fy = (double)(w->tny - 1);
+    int i = (int)floor(fx), j = (int)floor(fy);
+    if (i > w->tnx - 2) i = w->tnx - 2;
+    if (j > w->tny - 2) j = w->tny - 2;
+    double ax = fx - i, ay = fy - j;
+    double h00 = w->terr[(size_t)j * w->tnx + i];
+    double h10 = w->terr[(size_t)j * w->tnx + i + 1];
+    double h01 = w->terr[(size_t)(j + 1) * w->tnx + i];
+    double h11 = w->terr[(size_t)(j + 1) * w->tnx + i + 1];
+    return (1.0 - ay) * ((1.0 - ax) * h00 + ax * h10) + ay * ((1.0 - ax) * h01 + ax * h11);
+}
+
+static int outside_box(const orc_config *c, const double p[3]) {
+    for (int k = 0; k < 3; ++k)
+        if (p[k] < c->box_min[k] || p[k] > c->box_max[k]) return 1;
+    return 0;
+}
+
+/* Forward projection of one action: heading offset 2*pi*h/H from the goal
+ * bearing beta, horizontal speed v, climb rate c, for one step dt. */
+static void successor(const orc_config *c, const double s[3], double beta, int a, double out[3]) {
+    int v = a % c->n_speed;
+    int cl = (a / c->n_speed) % c->n_climb;
+    int h = a / (c->n_speed * c->n_climb);
+    double th = beta + 2.0 * M_PI * (double)h / (double)c->n_head;
+    double step = c->speed[v] * c->dt;
+    out[0] = s[0] + step * cos(th);
+    out[1] = s[1] + step * sin(th);
+    out[2] = s[2] + c->climb[cl] * c->dt;
+}
+
+static double goal_bearing(const double s[3], const double g[3]) {
+    double dx = g[0] - s[0], dy = g[1] - s[1];
+    if (dx == 0.0 && dy == 0.0) return 0.0;
+    return atan2(dy, dx);
+}
+
+/* Argmax with the tie band: the lowest index among values within tie_rel
+ * (relative) of the maximum.  -1 if every value is -inf. */
+static int select_action(const double *V, int A, double tie_rel) {
+    double vmax = -INFINITY;
+    for (int a = 0; a < A; ++a)
+        if (V[a] > vmax) vmax = V[a];
+    if (vmax == -INFINITY) return -1;
+    double thr = vmax - tie_rel * fabs(vmax);
+    for (int a = 0; a < A; ++a)
+        if (V[a] >= thr) return a;
+    return -1;
+}
+
+int orc_eval_step(const orc_world *w, const double s[3], const double g[3], int32_t t,
+                  double *V, double *G, double *I, double *T, double *dmin,
+                  int32_t *amb, int32_t *best) {
+    if (!w || !s || !g || t < 0) return ORC_E_INVAL;
+    const orc_config *c = &w->cfg;
+    const int A = c->n_head * c->n_climb * c->n_speed;
+    double *Vloc = (double *)malloc((size_t)A * sizeof(double));
+    if (!Vloc) return ORC_E_NOMEM;
+    const double beta = goal_bearing(s, g);
+    const double ell = w->ell;
+
+#pragma omp parallel for schedule(static)
+    for (int a = 0; a < A; ++a) {
+        double sp[3];
+        successor(c, s, beta, a, sp);
+
+        /* positive peak: the goal */
+        double dg = dist3(g, sp);
+        double Gp = fabs(c->r_goal) * pow(c->gamma, dg / ell);
+
+        /* negative peaks: one risk well per plan active at the successor's time */
+        double Ineg = 0.0, dnear = INFINITY;
+        int ambiguous = 0;
+        for (int j = 0; j < w->n_plans; ++j) {
+            double q[3];
+            if (!plan_point(&w->plans[j], t + 1, q)) continue;
+            double d = dist3(sp, q);
+            int in = d < c->R_intr;
+            double val = in ? fabs(c->r_intr) * pow(c->gamma_intr, d / ell) : 0.0;
+            if (val > Ineg) Ineg = val;
+            if (d < dnear) dnear = d;
+            if (fabs(d - c->R_intr) <= c->amb_band) ambiguous = 1;
+        }
+
+        /* negative peak: terrain clearance well */
+        double Tneg = 0.0;
+        if (w->terr) {
+            double clr = sp[2] - terrain_height(w, sp[0], sp[1]);
+            int in = clr < c->R_terr;
+            Tneg = in ? fabs(c->r_terr) * pow(c->gamma_terr, (clr > 0.0 ? clr : 0.0) / ell) : 0.0;
+            if (fabs(clr - c->R_terr) <= c->amb_band) ambiguous = 1;
+        }
+
+        double value = Gp - (Ineg > Tneg ? Ineg : Tneg);
+        if (outside_box(c, sp)) value = -INFINITY;
+
+        Vloc[a] = value;
+        if (V) V[a] = value;
+        if (G) G[a] = Gp;
+        if (I) I[a] = Ineg;
+        if (T) T[a] = Tneg;
+        if (dmin) dmin[a] = dnear;
+        if (amb) amb[a] = ambiguous;
+    }
+    if (best) *best = select_action(Vloc, A, c->tie_rel);
+    free(Vloc);
+    return 0;
+}
+
+/* Clearance below zero or any plan within R_sep at row t. */
+static int origin_blocked(const orc_world *w, const double s[3], int32_t t) {
+    const orc_config *c = &w->cfg;
+    if (outside_box(c, s)) return 1;
+    for (int j = 0; j < w->n_plans; ++j) {
+        double q[3];
+        if (plan_point(&w->plans[j], t, q) && dist3(s, q) < c->R_sep) return 1;
+    }
+    if (w->terr && s[2] - terrain_height(w, s[0], s[1]) < 0.0) return 1;
+    return 0;
+}
+
+int orc_plan(const orc_world *w, const double origin[3], const double goal[3], int32_t t0,
+             int32_t cap, double *xyz, int32_t *act, double *val,
+             int32_t *n_pts, int32_t *status) {
+    if (!w || !origin || !goal || t0 < 0 || cap < 1 || !xyz || !act || !val || !n_pts || !status)
+        return ORC_E_INVAL;
+    const orc_config *c = &w->cfg;
+    const int A = c->n_head * c->n_climb * c->n_speed;
+    double *V = (double *)malloc((size_t)A * sizeof(double));
+    double *I = (double *)malloc((size_t)A * sizeof(double));
+    double *T = (double *)malloc((size_t)A * sizeof(double));
+    if (!V || !I || !T) { free(V); free(I); free(T); return ORC_E_NOMEM; }
+
+    double s[3] = {origin[0], origin[1], origin[2]};
+    int32_t n = 0, t = t0, st = ORC_TIMEOUT;
+    xyz[0] = s[0]; xyz[1] = s[1]; xyz[2] = s[2];
+    act[0] = -1; val[0] = 0.0;
+    n = 1;
+    if (origin_blocked(w, s, t0)) {
+        st = ORC_REJECT_ORIGIN;
+    } else {
+        for (int32_t k = 0;; ++k) {
+            if (dist3(goal, s) <= w->ell) { st = ORC_OK; break; }
+            if (k == c->max_steps || n == cap) { st = ORC_TIMEOUT; break; }
+            int best = -1;
+            orc_eval_step(w, s, goal, t, V, NULL, I, T, NULL, NULL, &best);
+            if (best < 0) { st = ORC_NO_VALID_ACTION; break; }
+            double sp[3];
+            successor(c, s, goal_bearing(s, goal), best, sp);
+            s[0] = sp[0]; s[1] = sp[1]; s[2] = sp[2];
+            t += 1;
+            xyz[3 * n + 0] = s[0]; xyz[3 * n + 1] = s[1]; xyz[3 * n + 2] = s[2];
+            act[n] = best; val[n] = V[best];
+            n += 1;
+            /* stop at the first collision: inside an intruder well means a
+             * plan closer than the separation radius at this time */
+            if (I[best] > 0.0) { st = ORC_REJECT_SEPARATION; break; }
+            if (w->terr && s[2] - terrain_height(w, s[0], s[1]) < 0.0) { st = ORC_REJECT_TERRAIN; break; }
+        }
+    }
+    *n_pts = n;
+    *status = st;
+    free(V); free(I); free(T);
+    return 0;
+}
+
+int orc_commit(orc_world *w, int32_t t0, int32_t n, const double *xyz) {
+    if (!w || t0 < 0 || n < 1 || !xyz) return ORC_E_INVAL;
+    const orc_config *c = &w->cfg;
+    float *f = (float *)malloc((size_t)n * 3 * sizeof(float));
+    if (!f) return ORC_E_NOMEM;
+    for (int32_t k = 0; k < 3 * n; ++k) f[k] = (float)xyz[k];
+    for (int32_t k = 0; k < n; ++k) {
+        double x[3] = {(double)f[3 * k], (double)f[3 * k + 1], (double)f[3 * k + 2]};
+        for (int j = 0; j < w->n_plans; ++j) {
+            double q[3];
+            if (plan_point(&w->plans[j], t0 + k, q) && dist3(x, q) < c->R_sep) {
+                free(f);
+                return ORC_E_CONFLICT;
+            }
+        }
+        if (w->terr && x[2] - terrain_height(w, x[0], x[1]) < 0.0) {
+            free(f);
+            return ORC_E_CONFLICT;
+        }
+    }
+    int rc = orc_add_plan(w, t0, n, f);
+    free(f);
+    return rc;
+}

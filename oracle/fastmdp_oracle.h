@@ -1,0 +1,119 @@
+/*
+ * FP64 CPU oracle for FastMDP first-come-first-served pre-departure planning.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow reference that the HIP
+ * library is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it; the product path never does.
+ * It shares no code, header, table or helper with the HIP library.
+ *
+ * What it computes (Bertram, Zambreno & Wei, "Scalable FastMDP for
+ * Pre-departure Airspace Reservation and Strategic De-conflict"):
+ *   - per step, every action's successor state is scored by the closed-form
+ *     FastMDP value: a positive peak at the goal, r_g * gamma^(d/ell)
+ *     (Alg. 1, positive-peak loop; "Process positive rewards" kernel), minus
+ *     the larger of the intruder and terrain risk-well penalties, each a
+ *     maximum over peaks of [d < R] * |r| * gamma^(d/ell) (Alg. 1,
+ *     negative-peak loop; "Process negative intruder/terrain rewards"
+ *     kernels; "Compute value" kernel);
+ *   - the action with the largest value is taken (Alg. 1 argmax; "Select
+ *     best action" kernel) and the state advances ("Determine terminal
+ *     state" kernel);
+ *   - the loop runs until the goal is reached or a collision occurs, and only
+ *     a collision-free trajectory is accepted into the known-plan table
+ *     (Sec. V, Experimental Setup).
+ *
+ * Readings where the paper is silent (all stated in the design notes):
+ *   - distance in the discount exponent is measured in steps of
+ *     ell = max_speed * dt metres;
+ *   - one intruder peak per known plan, at that plan's own trajectory point
+ *     at the successor's time; window W = 1;
+ *   - kinematic action model: heading offsets 2*pi*h/H from the goal bearing,
+ *     climb rates and speeds from the config; action index a = (h*C + c)*S + v;
+ *   - the airspace box is a hard mask (value -inf outside);
+ *   - argmax ties: values within 1e-9 (relative) of the maximum are equal,
+ *     and the lowest action index among them is taken;
+ *   - separation radius R_sep is checked on the sampled time grid.
+ *
+ * Parity pins (tests/test_oracle_pins.py): the worked risk-well example of
+ * Fig. "riskwell", closed-form straight flight with no intruders, brute-force
+ * value iteration on a 1-D chain, a min-distance cross-formulation of the
+ * per-peak maximum, permutation and mirror invariances, the separation
+ * invariant, and the acceptance rule.  FastMDP-versus-value-iteration with
+ * risk wells is parity unpinned (the paper only claims a close
+ * approximation).
+ */
+#ifndef FASTMDP_ORACLE_H
+#define FASTMDP_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_ACT_DIM 32
+
+enum {
+    ORC_OK = 0,
+    ORC_REJECT_SEPARATION = 1,
+    ORC_REJECT_TERRAIN = 2,
+    ORC_REJECT_ORIGIN = 3,
+    ORC_TIMEOUT = 4,
+    ORC_NO_VALID_ACTION = 5
+};
+
+enum { ORC_E_INVAL = -1, ORC_E_CONFLICT = -4, ORC_E_NOMEM = -5 };
+
+typedef struct {
+    double box_min[3], box_max[3];
+    double dt;
+    double gamma, r_goal;                 /* positive peak (goal)          */
+    double r_intr, R_intr, gamma_intr;    /* intruder risk well            */
+    double R_sep;                         /* separation radius             */
+    double r_terr, R_terr, gamma_terr;    /* terrain risk well (clearance) */
+    int32_t n_head, n_climb, n_speed;
+    double climb[ORC_MAX_ACT_DIM];        /* m/s, index c                  */
+    double speed[ORC_MAX_ACT_DIM];        /* m/s, index v                  */
+    int32_t max_steps;
+    double tie_rel;                       /* argmax tie band (relative)    */
+    double amb_band;                      /* boundary-ambiguity band [m]   */
+} orc_config;
+
+typedef struct orc_world orc_world;
+
+int  orc_create(const orc_config *cfg, orc_world **out);
+void orc_destroy(orc_world *w);
+
+/* Append a plan without validation (known plans loaded from the database). */
+int  orc_add_plan(orc_world *w, int32_t t0, int32_t n, const float *xyz);
+int  orc_num_plans(const orc_world *w);
+
+/* Heightmap h[j*nx+i] at (x0 + i*cell, y0 + j*cell); bilinear, clamped. */
+int  orc_set_terrain(orc_world *w, int32_t nx, int32_t ny, const float *h,
+                     double x0, double y0, double cell);
+
+/* Score every action from state s at time row t against the plans active at
+ * row t+1.  Outputs (length A each, any may be NULL): V value, G goal term,
+ * I intruder term, T terrain term, dmin nearest-plan distance (inf if none),
+ * amb 1 if a plan distance or the clearance lies within amb_band of its
+ * radius.  *best = chosen action or -1 if every value is -inf. */
+int  orc_eval_step(const orc_world *w, const double s[3], const double g[3], int32_t t,
+                   double *V, double *G, double *I, double *T, double *dmin,
+                   int32_t *amb, int32_t *best);
+
+/* Plan one request from origin at row t0 towards goal.  Writes up to cap
+ * points: xyz[k*3..], act[k] (-1 for the origin), val[k] (0 for the origin).
+ * Returns 0 and sets *n_pts and *status, or a negative error. */
+int  orc_plan(const orc_world *w, const double origin[3], const double goal[3], int32_t t0,
+              int32_t cap, double *xyz, int32_t *act, double *val,
+              int32_t *n_pts, int32_t *status);
+
+/* Validate a trajectory (rounded to FP32, the table's storage format)
+ * against every plan in the table and the terrain; append it if clear.
+ * Returns 0, or ORC_E_CONFLICT with the table unchanged. */
+int  orc_commit(orc_world *w, int32_t t0, int32_t n, const double *xyz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
