@@ -1,0 +1,568 @@
+// api.hip -- host side of libfastmdp: the C ABI declared in include/fastmdp.h.
+//
+// The context owns the device state: the time-major SoA known-plan table,
+// the terrain heightmap, per-slot trajectory buffers and small scratch.  A
+// host mirror of the per-row entry counts is kept for capacity checks and
+// for loading plans.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "fastmdp.h"
+#include "planner.h"
+
+using fmdp::DevCfg;
+using fmdp::DevTable;
+using fmdp::EvalOut;
+using fmdp::Slot;
+using fmdp::Traj;
+
+struct fastmdp_ctx {
+    fastmdp_config cfg{};
+    DevCfg dc{};
+    DevTable tb{};
+    int A = 0;
+    hipStream_t own = nullptr, stream = nullptr;
+    std::vector<int> hRowN;
+    int n_plans = 0;
+    float *dTerr = nullptr;
+    int max_slots = 1, stride = 0;
+    Slot *dSlots = nullptr;
+    int *dList = nullptr, *dOrder = nullptr, *dNdone = nullptr;
+    Traj tr{};
+    double *dEv = nullptr;        // 4*A eval outputs
+    int *dBest = nullptr;
+    float *dPts = nullptr;        // stride*3 commit staging
+    int *dFlag = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::mutex mu;
+    // counters of the last call
+    long long st_pairs = 0, st_steps = 0, st_resumes = 0, st_launches = 0;
+    double st_ms = 0.0;
+};
+
+namespace {
+
+#define HIP_TRY(x)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess) {                                                                     \
+            std::fprintf(stderr, "libfastmdp: %s failed: %s\n", #x, hipGetErrorString(e_));         \
+            return FASTMDP_E_DEVICE;                                                                \
+        }                                                                                           \
+    } while (0)
+
+template <class T>
+int dev_alloc(T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) return 0;
+    if (hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        return FASTMDP_E_NOMEM;
+    }
+    return 0;
+}
+
+void free_all(fastmdp_ctx *c) {
+    hipFree(c->tb.X); hipFree(c->tb.Y); hipFree(c->tb.Z); hipFree(c->tb.rowN);
+    hipFree(c->dTerr);
+    hipFree(c->dSlots); hipFree(c->dList); hipFree(c->dOrder); hipFree(c->dNdone);
+    hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen);
+    hipFree(c->dEv); hipFree(c->dBest); hipFree(c->dPts); hipFree(c->dFlag);
+    if (c->e0) hipEventDestroy(c->e0);
+    if (c->e1) hipEventDestroy(c->e1);
+    if (c->own) hipStreamDestroy(c->own);
+}
+
+int check_cfg(const fastmdp_config *c) {
+    if (!c) return FASTMDP_E_INVAL;
+    if (c->n_head < 1 || c->n_head > fmdp::kMaxHeads) return FASTMDP_E_INVAL;
+    if (c->n_climb < 1 || c->n_climb > FASTMDP_MAX_ACT_DIM) return FASTMDP_E_INVAL;
+    if (c->n_speed < 1 || c->n_speed > FASTMDP_MAX_ACT_DIM) return FASTMDP_E_INVAL;
+    if ((long)c->n_head * c->n_climb * c->n_speed > fmdp::kMaxActions) return FASTMDP_E_INVAL;
+    if (!(c->dt > 0.0) || !(c->gamma > 0.0 && c->gamma < 1.0)) return FASTMDP_E_INVAL;
+    if (!(c->gamma_intr > 0.0 && c->gamma_intr < 1.0) || !(c->gamma_terr > 0.0 && c->gamma_terr < 1.0))
+        return FASTMDP_E_INVAL;
+    for (int v = 0; v < c->n_speed; ++v)
+        if (!(c->speed[v] > 0.0)) return FASTMDP_E_INVAL;
+    if (c->max_steps < 1 || c->plan_capacity < 1 || c->max_rows < 2) return FASTMDP_E_INVAL;
+    if (!(c->tie_rel >= 0.0)) return FASTMDP_E_INVAL;
+    return 0;
+}
+
+void make_devcfg(const fastmdp_config &c, DevCfg &d) {
+    std::memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 3; ++k) { d.box_lo[k] = c.box_min[k]; d.box_hi[k] = c.box_max[k]; }
+    double vmax = 0.0, cmax = 0.0;
+    for (int v = 0; v < c.n_speed; ++v) vmax = std::max(vmax, c.speed[v]);
+    for (int k = 0; k < c.n_climb; ++k) cmax = std::max(cmax, std::fabs(c.climb[k]));
+    d.dt = c.dt;
+    d.ell = vmax * c.dt;
+    d.gamma = c.gamma; d.r_goal = c.r_goal;
+    d.r_intr = c.r_intr; d.R_intr = c.R_intr; d.gamma_intr = c.gamma_intr;
+    d.R_sep = c.R_sep;
+    d.r_terr = c.r_terr; d.R_terr = c.R_terr; d.gamma_terr = c.gamma_terr;
+    for (int k = 0; k < FASTMDP_MAX_ACT_DIM; ++k) {
+        d.climb[k] = c.climb[k];
+        d.speed[k] = c.speed[k];
+        d.climb_f[k] = (float)c.climb[k];
+        d.kv[k] = (float)(-2.0 * c.speed[k] * c.dt);
+    }
+    d.zeta_scale = (float)(-2.0 * c.dt);
+    d.tie_rel = c.tie_rel;
+    const double max_step = std::sqrt(vmax * vmax + cmax * cmax) * c.dt;
+    d.reach = std::max(c.R_intr, c.R_sep) + max_step + 1.0;
+    d.n_head = c.n_head; d.n_climb = c.n_climb; d.n_speed = c.n_speed;
+    d.n_actions = c.n_head * c.n_climb * c.n_speed;
+    const int mid = c.n_climb / 2;
+    d.zero_climb = (c.climb[mid] == 0.0) ? mid : -1;
+    d.max_steps = c.max_steps;
+}
+
+int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int validate, const EvalOut &ev) {
+    HIP_TRY(hipEventRecord(c->e0, c->stream));
+    hipError_t e = fmdp::launch_planner(nblk, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate, ev);
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "libfastmdp: planner launch failed: %s\n", hipGetErrorString(e));
+        return FASTMDP_E_DEVICE;
+    }
+    HIP_TRY(hipEventRecord(c->e1, c->stream));
+    HIP_TRY(hipEventSynchronize(c->e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->e0, c->e1));
+    c->st_ms += ms;
+    c->st_launches += 1;
+    return 0;
+}
+
+void reset_stats(fastmdp_ctx *c) {
+    c->st_pairs = c->st_steps = c->st_resumes = c->st_launches = 0;
+    c->st_ms = 0.0;
+}
+
+Slot fresh_slot(const fastmdp_request &r, int req_index) {
+    Slot s;
+    std::memset(&s, 0, sizeof(s));
+    s.origin[0] = r.origin.x; s.origin[1] = r.origin.y; s.origin[2] = r.origin.z;
+    s.goal[0] = r.goal.x; s.goal[1] = r.goal.y; s.goal[2] = r.goal.z;
+    s.t0 = r.t0;
+    s.n_points = 0;
+    s.status = fmdp::kRunning;
+    s.req = req_index;
+    s.resume_at = -1;
+    return s;
+}
+
+int copy_plan_out(fastmdp_ctx *c, int slot, const Slot &s, fastmdp_plan *out) {
+    const int n = s.n_points;
+    if (out->capacity < n || !out->xyz || !out->action || !out->value) return FASTMDP_E_CAPACITY;
+    const size_t base = (size_t)slot * c->stride;
+    HIP_TRY(hipMemcpyAsync(out->xyz, c->tr.xyz + base * 3, (size_t)n * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(out->action, c->tr.act + base, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(out->value, c->tr.val + base, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    out->status = s.status;
+    out->t0 = s.t0;
+    out->n_points = n;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
+    if (!out) return FASTMDP_E_INVAL;
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    fastmdp_ctx *c = new (std::nothrow) fastmdp_ctx();
+    if (!c) return FASTMDP_E_NOMEM;
+    c->cfg = *cfg;
+    make_devcfg(*cfg, c->dc);
+    if (!fmdp::planner_shape_supported(cfg->n_climb, cfg->n_speed, c->dc.zero_climb)) {
+        delete c;
+        return FASTMDP_E_INVAL;
+    }
+    c->A = c->dc.n_actions;
+    c->max_slots = std::max(1, cfg->max_slots);
+    c->stride = cfg->max_steps + 1;
+    c->tb.cap = cfg->plan_capacity;
+    c->tb.rows = cfg->max_rows;
+    const size_t tsz = (size_t)cfg->max_rows * cfg->plan_capacity;
+    const size_t ssz = (size_t)c->max_slots * c->stride;
+    rc = 0;
+    rc = rc ? rc : dev_alloc(&c->tb.X, tsz);
+    rc = rc ? rc : dev_alloc(&c->tb.Y, tsz);
+    rc = rc ? rc : dev_alloc(&c->tb.Z, tsz);
+    rc = rc ? rc : dev_alloc(&c->tb.rowN, (size_t)cfg->max_rows);
+    rc = rc ? rc : dev_alloc(&c->dSlots, (size_t)c->max_slots);
+    rc = rc ? rc : dev_alloc(&c->dList, (size_t)c->max_slots);
+    rc = rc ? rc : dev_alloc(&c->dOrder, (size_t)c->max_slots);
+    rc = rc ? rc : dev_alloc(&c->dNdone, (size_t)1);
+    rc = rc ? rc : dev_alloc(&c->tr.xyz, ssz * 3);
+    rc = rc ? rc : dev_alloc(&c->tr.act, ssz);
+    rc = rc ? rc : dev_alloc(&c->tr.val, ssz);
+    rc = rc ? rc : dev_alloc(&c->tr.seen, ssz);
+    rc = rc ? rc : dev_alloc(&c->dEv, (size_t)4 * c->A);
+    rc = rc ? rc : dev_alloc(&c->dBest, (size_t)1);
+    rc = rc ? rc : dev_alloc(&c->dPts, (size_t)c->stride * 3);
+    rc = rc ? rc : dev_alloc(&c->dFlag, (size_t)1);
+    if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
+    if (!rc && hipEventCreate(&c->e0) != hipSuccess) rc = FASTMDP_E_DEVICE;
+    if (!rc && hipEventCreate(&c->e1) != hipSuccess) rc = FASTMDP_E_DEVICE;
+    if (rc) {
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    c->stream = c->own;
+    c->tr.stride = c->stride;
+    c->hRowN.assign(cfg->max_rows, 0);
+    if (fmdp::launch_fill_int(c->tb.rowN, 0, cfg->max_rows, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return FASTMDP_E_DEVICE;
+    }
+    *out = c;
+    return 0;
+}
+
+void fastmdp_destroy(fastmdp_ctx *ctx) {
+    if (!ctx) return;
+    hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+}
+
+int fastmdp_set_stream(fastmdp_ctx *ctx, void *hip_stream) {
+    if (!ctx) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->own;
+    return 0;
+}
+
+int fastmdp_load_plans(fastmdp_ctx *ctx, int32_t n, const int32_t *t0, const int32_t *len, const float *xyz) {
+    if (!ctx || n < 0 || (n > 0 && (!t0 || !len || !xyz))) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    size_t total = 0;
+    for (int j = 0; j < n; ++j) {
+        if (t0[j] < 0 || len[j] < 1) return FASTMDP_E_INVAL;
+        if ((long)t0[j] + len[j] > ctx->tb.rows) return FASTMDP_E_CAPACITY;
+        total += (size_t)len[j];
+    }
+    std::vector<int> rowN = ctx->hRowN;
+    std::vector<int> rows(total), cols(total);
+    size_t p = 0;
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < len[j]; ++k, ++p) {
+            const int r = t0[j] + k;
+            if (rowN[r] >= ctx->tb.cap) return FASTMDP_E_CAPACITY;
+            rows[p] = r;
+            cols[p] = rowN[r]++;
+        }
+    if (total) {
+        float *dP = nullptr;
+        int *dR = nullptr, *dC = nullptr;
+        int rc = dev_alloc(&dP, total * 3);
+        rc = rc ? rc : dev_alloc(&dR, total);
+        rc = rc ? rc : dev_alloc(&dC, total);
+        if (rc) { hipFree(dP); hipFree(dR); hipFree(dC); return rc; }
+        hipError_t e = hipMemcpyAsync(dP, xyz, total * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dR, rows.data(), total * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dC, cols.data(), total * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = fmdp::launch_scatter_points(ctx->tb, dP, dR, dC, (int)total, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->tb.rowN, rowN.data(), rowN.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        hipFree(dP); hipFree(dR); hipFree(dC);
+        if (e != hipSuccess) {
+            std::fprintf(stderr, "libfastmdp: load_plans: %s\n", hipGetErrorString(e));
+            return FASTMDP_E_DEVICE;
+        }
+    }
+    ctx->hRowN.swap(rowN);
+    ctx->n_plans += n;
+    return 0;
+}
+
+int fastmdp_set_terrain(fastmdp_ctx *ctx, int32_t nx, int32_t ny, const float *h, double x0, double y0, double cell) {
+    if (!ctx || nx < 2 || ny < 2 || !h || !(cell > 0.0)) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    float *d = nullptr;
+    int rc = dev_alloc(&d, (size_t)nx * ny);
+    if (rc) return rc;
+    if (hipMemcpy(d, h, (size_t)nx * ny * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(d);
+        return FASTMDP_E_DEVICE;
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    hipFree(ctx->dTerr);
+    ctx->dTerr = d;
+    ctx->tb.terr = d;
+    ctx->tb.tnx = nx; ctx->tb.tny = ny;
+    ctx->tb.tx0 = x0; ctx->tb.ty0 = y0; ctx->tb.tcell = cell;
+    return 0;
+}
+
+int fastmdp_eval_step(fastmdp_ctx *ctx, const fastmdp_state *state, double *values, double *goal_term,
+                      double *intr_term, double *terr_term, int32_t *best) {
+    if (!ctx || !state || state->t < 0) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    reset_stats(ctx);
+    fastmdp_request r{};
+    r.origin = state->pos;
+    r.goal = state->goal;
+    r.t0 = state->t;
+    Slot s = fresh_slot(r, 0);
+    HIP_TRY(hipMemcpyAsync(ctx->dSlots, &s, sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+    const int A = ctx->A;
+    EvalOut ev{ctx->dEv, ctx->dEv + A, ctx->dEv + 2 * A, ctx->dEv + 3 * A, ctx->dBest};
+    int rc = timed_planner(ctx, 1, nullptr, 1, 0, ev);
+    if (rc) return rc;
+    std::vector<double> h(4 * (size_t)A);
+    int b = -1;
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->dEv, h.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(&b, ctx->dBest, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(&s, ctx->dSlots, sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (values) std::memcpy(values, h.data(), A * sizeof(double));
+    if (goal_term) std::memcpy(goal_term, h.data() + A, A * sizeof(double));
+    if (intr_term) std::memcpy(intr_term, h.data() + 2 * A, A * sizeof(double));
+    if (terr_term) std::memcpy(terr_term, h.data() + 3 * A, A * sizeof(double));
+    if (best) *best = b;
+    ctx->st_pairs = s.pairs;
+    ctx->st_steps = s.steps;
+    return 0;
+}
+
+int fastmdp_plan_request(fastmdp_ctx *ctx, const fastmdp_request *req, fastmdp_plan *out) {
+    if (!ctx || !req || !out || req->t0 < 0) return FASTMDP_E_INVAL;
+    if (out->capacity < ctx->stride || !out->xyz || !out->action || !out->value) return FASTMDP_E_CAPACITY;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    reset_stats(ctx);
+    Slot s = fresh_slot(*req, 0);
+    HIP_TRY(hipMemcpyAsync(ctx->dSlots, &s, sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+    EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = timed_planner(ctx, 1, nullptr, ctx->cfg.max_steps + 1, 0, none);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(&s, ctx->dSlots, sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    rc = copy_plan_out(ctx, 0, s, out);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->st_pairs = s.pairs;
+    ctx->st_steps = s.steps;
+    return 0;
+}
+
+int fastmdp_commit_plan(fastmdp_ctx *ctx, const fastmdp_plan *plan) {
+    if (!ctx || !plan || !plan->xyz || plan->n_points < 1 || plan->t0 < 0) return FASTMDP_E_INVAL;
+    if (plan->status != FASTMDP_OK) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int n = plan->n_points, t0 = plan->t0;
+    if ((long)t0 + n > ctx->tb.rows || n > ctx->stride) return FASTMDP_E_CAPACITY;
+    for (int k = 0; k < n; ++k)
+        if (ctx->hRowN[t0 + k] >= ctx->tb.cap) return FASTMDP_E_CAPACITY;
+    std::vector<float> pts((size_t)n * 3);
+    for (size_t i = 0; i < pts.size(); ++i) pts[i] = (float)plan->xyz[i];
+    HIP_TRY(hipMemcpyAsync(ctx->dPts, pts.data(), pts.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(fmdp::launch_fill_int(ctx->dFlag, 0, 1, ctx->stream));
+    HIP_TRY(fmdp::launch_commit_check(ctx->dc, ctx->tb, ctx->dPts, t0, n, ctx->dFlag, ctx->stream));
+    HIP_TRY(fmdp::launch_commit_append(ctx->tb, ctx->dPts, t0, n, ctx->dFlag, ctx->stream));
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, ctx->dFlag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (flag & 2) return FASTMDP_E_CAPACITY;
+    if (flag) return FASTMDP_E_CONFLICT;
+    for (int k = 0; k < n; ++k) ctx->hRowN[t0 + k] += 1;
+    ctx->n_plans += 1;
+    return 0;
+}
+
+int fastmdp_num_plans(const fastmdp_ctx *ctx) { return ctx ? ctx->n_plans : FASTMDP_E_INVAL; }
+
+int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, fastmdp_plan *plans,
+                      int32_t *committed) {
+    if (!ctx || n < 0 || (n > 0 && (!reqs || !plans || !committed))) return FASTMDP_E_INVAL;
+    for (int i = 0; i < n; ++i) {
+        if (reqs[i].t0 < 0) return FASTMDP_E_INVAL;
+        if (plans[i].capacity < ctx->stride || !plans[i].xyz || !plans[i].action || !plans[i].value)
+            return FASTMDP_E_CAPACITY;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    reset_stats(ctx);
+    const int S = std::min(ctx->max_slots, std::max(n, 1));
+    const int budget = 256;
+    std::vector<Slot> hs(S);
+    std::vector<int> slot_req(S, -1);        // request held by each slot
+    std::vector<int> req_slot(n, -1);
+    int next_req = 0, next_commit = 0;
+    std::vector<int> list, order;
+    while (next_commit < n) {
+        // admit requests into free slots (in request order)
+        bool dirty = false;
+        for (int s = 0; s < S && next_req < n; ++s)
+            if (slot_req[s] < 0) {
+                hs[s] = fresh_slot(reqs[next_req], next_req);
+                slot_req[s] = next_req;
+                req_slot[next_req] = s;
+                ++next_req;
+                dirty = true;
+            }
+        if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs.data(), S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+        // plan every running slot for up to `budget` steps
+        list.clear();
+        for (int s = 0; s < S; ++s)
+            if (slot_req[s] >= 0 && hs[s].status == fmdp::kRunning) list.push_back(s);
+        if (!list.empty()) {
+            HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
+                                   ctx->stream));
+            EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
+            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, none);
+            if (rc) return rc;
+            HIP_TRY(hipMemcpyAsync(hs.data(), ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+        }
+        // the finished prefix in request order goes to the sequencer
+        order.clear();
+        for (int r = next_commit; r < next_req; ++r) {
+            const int s = req_slot[r];
+            if (hs[s].status == fmdp::kRunning) break;
+            order.push_back(s);
+        }
+        if (order.empty()) continue;
+        HIP_TRY(hipMemcpyAsync(ctx->dOrder, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice,
+                               ctx->stream));
+        HIP_TRY(fmdp::launch_fcfs_sequencer(ctx->dc, ctx->tb, ctx->dSlots, ctx->dOrder, (int)order.size(), ctx->tr,
+                                            ctx->dNdone, ctx->stream));
+        int done = 0;
+        HIP_TRY(hipMemcpyAsync(&done, ctx->dNdone, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(hs.data(), ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        for (int q = 0; q < done; ++q) {
+            const int s = order[q];
+            const int r = slot_req[s];
+            int rc = copy_plan_out(ctx, s, hs[s], &plans[r]);
+            if (rc) return rc;
+            committed[r] = hs[s].committed;
+            if (hs[s].committed) {
+                for (int k = 0; k < hs[s].n_points; ++k) ctx->hRowN[hs[s].t0 + k] += 1;
+                ctx->n_plans += 1;
+            }
+            ctx->st_pairs += hs[s].pairs;
+            ctx->st_steps += hs[s].steps;
+            slot_req[s] = -1;
+            ++next_commit;
+        }
+        if (done < (int)order.size()) ctx->st_resumes += 1;   // order[done] resumes planning
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    return 0;
+}
+
+int fastmdp_last_stats(const fastmdp_ctx *ctx, int64_t *pairs, int64_t *steps, int64_t *resumes, int64_t *launches,
+                       double *kernel_ms) {
+    if (!ctx) return FASTMDP_E_INVAL;
+    if (pairs) *pairs = ctx->st_pairs;
+    if (steps) *steps = ctx->st_steps;
+    if (resumes) *resumes = ctx->st_resumes;
+    if (launches) *launches = ctx->st_launches;
+    if (kernel_ms) *kernel_ms = ctx->st_ms;
+    return 0;
+}
+
+// Checkpoint file: "FMDPTAB1", rows, cap, n_plans, rowN[rows], then for each
+// row its rowN entries of x, y and z (FP32).
+int fastmdp_save_table(fastmdp_ctx *ctx, const char *path) {
+    if (!ctx || !path) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int rows = ctx->tb.rows, cap = ctx->tb.cap;
+    std::vector<float> buf((size_t)cap);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return FASTMDP_E_IO;
+    int hdr[3] = {rows, cap, ctx->n_plans};
+    bool ok = std::fwrite("FMDPTAB1", 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int), 3, f) == 3 &&
+              std::fwrite(ctx->hRowN.data(), sizeof(int), rows, f) == (size_t)rows;
+    for (int r = 0; ok && r < rows; ++r) {
+        const int m = ctx->hRowN[r];
+        if (!m) continue;
+        float *src[3] = {ctx->tb.X, ctx->tb.Y, ctx->tb.Z};
+        for (int a = 0; a < 3 && ok; ++a) {
+            if (hipMemcpy(buf.data(), src[a] + (size_t)r * cap, m * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
+                std::fclose(f);
+                return FASTMDP_E_DEVICE;
+            }
+            ok = std::fwrite(buf.data(), sizeof(float), m, f) == (size_t)m;
+        }
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? 0 : FASTMDP_E_IO;
+}
+
+int fastmdp_load_table(fastmdp_ctx *ctx, const char *path) {
+    if (!ctx || !path) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return FASTMDP_E_IO;
+    char magic[8];
+    int hdr[3];
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "FMDPTAB1", 8) != 0 ||
+        std::fread(hdr, sizeof(int), 3, f) != 3) {
+        std::fclose(f);
+        return FASTMDP_E_IO;
+    }
+    const int rows = hdr[0], cap = hdr[1];
+    if (rows != ctx->tb.rows || cap > ctx->tb.cap || hdr[2] < 0) {
+        std::fclose(f);
+        return FASTMDP_E_CAPACITY;
+    }
+    std::vector<int> rowN(rows);
+    if (std::fread(rowN.data(), sizeof(int), rows, f) != (size_t)rows) {
+        std::fclose(f);
+        return FASTMDP_E_IO;
+    }
+    std::vector<float> buf((size_t)ctx->tb.cap);
+    for (int r = 0; r < rows; ++r) {
+        const int m = rowN[r];
+        if (m < 0 || m > ctx->tb.cap) { std::fclose(f); return FASTMDP_E_IO; }
+        float *dst[3] = {ctx->tb.X, ctx->tb.Y, ctx->tb.Z};
+        for (int a = 0; a < 3 && m; ++a) {
+            if (std::fread(buf.data(), sizeof(float), m, f) != (size_t)m) { std::fclose(f); return FASTMDP_E_IO; }
+            if (hipMemcpy(dst[a] + (size_t)r * ctx->tb.cap, buf.data(), m * sizeof(float), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+                std::fclose(f);
+                return FASTMDP_E_DEVICE;
+            }
+        }
+    }
+    std::fclose(f);
+    if (hipMemcpy(ctx->tb.rowN, rowN.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return FASTMDP_E_DEVICE;
+    ctx->hRowN.swap(rowN);
+    ctx->n_plans = hdr[2];
+    return 0;
+}
+
+const char *fastmdp_strerror(int code) {
+    switch (code) {
+        case 0: return "ok";
+        case FASTMDP_E_INVAL: return "invalid argument or unsupported configuration";
+        case FASTMDP_E_CAPACITY: return "table or buffer capacity exceeded";
+        case FASTMDP_E_DEVICE: return "HIP runtime error";
+        case FASTMDP_E_CONFLICT: return "commit refused: separation or terrain conflict";
+        case FASTMDP_E_NOMEM: return "out of memory";
+        case FASTMDP_E_IO: return "file input/output error";
+        default: return "unknown code";
+    }
+}
+
+}  // extern "C"

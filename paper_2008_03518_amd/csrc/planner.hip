@@ -1,0 +1,428 @@
+// planner.hip -- device code of the FastMDP first-come-first-served planner
+// for gfx950 (MI355X).
+//
+// One workgroup plans one request ("slot"), persistent over time steps.  Per
+// step (the kernel pipeline of Sec. IV fused into one workgroup):
+//   1. bearing to the goal and the per-heading direction cosines (FP64);
+//   2. the known-plan table row of the successor's time is staged from HBM
+//      into LDS in tiles, each plan as (q_x, q_y, -2 dt q_z, |q|^2) with
+//      q = p - s relative to the current state (FP64 subtraction, FP32 store);
+//   3. the intruder sweep (the "Process negative intruder rewards" kernel):
+//      every lane owns one heading and all climb x speed actions of it and a
+//      slice of the staged plans, and keeps, per action, the minimum over
+//      plans of |q - Delta_a|^2 - |Delta_a|^2 = |q|^2 - 2 Delta_a . q.
+//      Because gamma^d falls with d, the largest risk-well penalty over the
+//      plans is the one of the nearest plan, so the per-peak maximum of the
+//      paper is this minimum followed by one well evaluation per action;
+//   4. per action (FP64): goal peak, intruder well from the nearest plan,
+//      terrain clearance well, value = goal - max(penalties), box mask
+//      (kernels "Process positive rewards", "Process negative terrain
+//      rewards", "Compute value");
+//   5. argmax by wavefront shuffle reductions ("Select best action");
+//   6. state advance, goal capture, collision checks and trajectory append
+//      ("Determine terminal state").
+#include "planner.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace fmdp {
+
+__device__ __forceinline__ bool outside_box(const DevCfg &c, double x, double y, double z) {
+    return x < c.box_lo[0] || x > c.box_hi[0] || y < c.box_lo[1] || y > c.box_hi[1] ||
+           z < c.box_lo[2] || z > c.box_hi[2];
+}
+
+// Terrain height: bilinear in the vertex grid, position clamped to the grid.
+__device__ double terrain_height(const DevTable &tb, double x, double y) {
+    double fx = (x - tb.tx0) / tb.tcell;
+    double fy = (y - tb.ty0) / tb.tcell;
+    fx = fmin(fmax(fx, 0.0), (double)(tb.tnx - 1));
+    fy = fmin(fmax(fy, 0.0), (double)(tb.tny - 1));
+    int i = (int)floor(fx), j = (int)floor(fy);
+    i = i > tb.tnx - 2 ? tb.tnx - 2 : i;
+    j = j > tb.tny - 2 ? tb.tny - 2 : j;
+    const double ax = fx - i, ay = fy - j;
+    const float *h = tb.terr + (size_t)j * tb.tnx + i;
+    const double h00 = h[0], h10 = h[1], h01 = h[tb.tnx], h11 = h[tb.tnx + 1];
+    return (1.0 - ay) * ((1.0 - ax) * h00 + ax * h10) + ay * ((1.0 - ax) * h01 + ax * h11);
+}
+
+struct Scored {
+    double x, y, z;     // successor
+    double G, I, T, V;  // goal term, intruder well, terrain well, value
+    double clr;         // terrain clearance (inf without terrain)
+};
+
+// Score action a from state s given the per-heading cosines and the nearest
+// plan's squared-distance offset m (min over plans of |q|^2 - 2 Delta.q).
+__device__ Scored score_action(const DevCfg &c, const DevTable &tb, int a, const double s[3],
+                               const double g[3], double cs, double sn, float m) {
+    Scored r;
+    const int v = a % c.n_speed;
+    const int cl = (a / c.n_speed) % c.n_climb;
+    const double step = c.speed[v] * c.dt;
+    const double dz = c.climb[cl] * c.dt;
+    r.x = s[0] + step * cs;
+    r.y = s[1] + step * sn;
+    r.z = s[2] + dz;
+    const double ex = g[0] - r.x, ey = g[1] - r.y, ez = g[2] - r.z;
+    r.G = fabs(c.r_goal) * pow(c.gamma, sqrt(ex * ex + ey * ey + ez * ez) / c.ell);
+    // squared distance to the nearest plan: m + |Delta|^2
+    const double d2 = (double)m + step * step + dz * dz;
+    r.I = 0.0;
+    if (d2 < c.R_intr * c.R_intr)
+        r.I = fabs(c.r_intr) * pow(c.gamma_intr, sqrt(fmax(d2, 0.0)) / c.ell);
+    r.T = 0.0;
+    r.clr = INFINITY;
+    if (tb.terr) {
+        r.clr = r.z - terrain_height(tb, r.x, r.y);
+        if (r.clr < c.R_terr) r.T = fabs(c.r_terr) * pow(c.gamma_terr, fmax(r.clr, 0.0) / c.ell);
+    }
+    r.V = r.G - fmax(r.I, r.T);
+    if (outside_box(c, r.x, r.y, r.z)) r.V = -INFINITY;
+    return r;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+template <int NC, int NV, int ZC>
+__global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTable tb, Slot *slots,
+                                                               const int *slot_list, Traj tr, int budget,
+                                                               int validate, EvalOut ev) {
+    constexpr int NW = kPlanThreads / 64;
+    __shared__ float4 tile[kTile];              // staged plans; reused for the slice reduction
+    __shared__ double sV[kMaxActions];
+    __shared__ float sM[kMaxActions];
+    __shared__ double sCos[kMaxHeads], sSin[kMaxHeads];
+    __shared__ double st_s[3];
+    __shared__ int st_n, st_status, st_flag;
+    __shared__ double red_d[NW];
+    __shared__ int red_i[NW];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int slot = slot_list ? slot_list[blockIdx.x] : (int)blockIdx.x;
+    Slot &S = slots[slot];
+    const bool eval = ev.V != nullptr || ev.best != nullptr;
+
+    const int H = cfg.n_head, A = cfg.n_actions;
+    const int n_slices = kPlanThreads / H;
+    const int my_h = tid % H, my_slice = tid / H;
+    const bool sweeper = tid < n_slices * H;
+
+    const double g[3] = {S.goal[0], S.goal[1], S.goal[2]};
+    const int t0 = S.t0;
+    const size_t pt_base = (size_t)slot * tr.stride;
+
+    if (tid == 0) {
+        const int n = eval ? 0 : S.n_points;
+        if (n == 0) {
+            st_s[0] = S.origin[0]; st_s[1] = S.origin[1]; st_s[2] = S.origin[2];
+        } else {
+            const double *p = tr.xyz + (pt_base + n - 1) * 3;
+            st_s[0] = p[0]; st_s[1] = p[1]; st_s[2] = p[2];
+        }
+        st_n = n;
+        st_status = kRunning;
+        st_flag = 0;
+    }
+    __syncthreads();
+
+    // Origin check of a fresh request: inside the box, clear of terrain, and
+    // no plan active at the departure row closer than R_sep.
+    if (!eval && st_n == 0) {
+        const double o[3] = {st_s[0], st_s[1], st_s[2]};
+        const int n_row = t0 < tb.rows ? tb.rowN[t0] : 0;
+        const size_t rb = (size_t)t0 * tb.cap;
+        int hit = 0;
+        for (int j = tid; j < n_row; j += kPlanThreads) {
+            const double dx = (double)tb.X[rb + j] - o[0];
+            const double dy = (double)tb.Y[rb + j] - o[1];
+            const double dz = (double)tb.Z[rb + j] - o[2];
+            if (sqrt(dx * dx + dy * dy + dz * dz) < cfg.R_sep) hit = 1;
+        }
+        if (hit) st_flag = 1;        // benign race: every writer stores 1
+        __syncthreads();
+        if (tid == 0) {
+            bool blocked = st_flag != 0 || outside_box(cfg, o[0], o[1], o[2]);
+            if (tb.terr && o[2] - terrain_height(tb, o[0], o[1]) < 0.0) blocked = true;
+            double *p = tr.xyz + pt_base * 3;
+            p[0] = o[0]; p[1] = o[1]; p[2] = o[2];
+            tr.act[pt_base] = -1;
+            tr.val[pt_base] = 0.0;
+            tr.seen[pt_base] = n_row;
+            st_n = 1;
+            if (blocked) st_status = FASTMDP_REJECT_ORIGIN;
+        }
+        __syncthreads();
+    }
+
+    // per-lane sweep constants
+    float kv[NV], clf[NC];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) kv[v] = cfg.kv[v];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) clf[c] = cfg.climb_f[c];
+
+    long long pairs = 0;
+    int steps_here = 0;
+
+    for (;;) {
+        if (st_status != kRunning) break;                 // uniform (LDS, after a barrier)
+        const int n = st_n;
+        const int k = eval ? 0 : n - 1;                    // steps taken so far
+        const int t = eval ? t0 : t0 + k;
+        const double s[3] = {st_s[0], st_s[1], st_s[2]};
+        if (!eval) {
+            const double ex = g[0] - s[0], ey = g[1] - s[1], ez = g[2] - s[2];
+            if (sqrt(ex * ex + ey * ey + ez * ez) <= cfg.ell) {
+                __syncthreads();
+                if (tid == 0) st_status = FASTMDP_OK;
+                break;
+            }
+            if (k >= cfg.max_steps) {
+                __syncthreads();
+                if (tid == 0) st_status = FASTMDP_TIMEOUT;
+                break;
+            }
+            if (steps_here >= budget) break;               // resumable: stays running
+        }
+
+        // 1. bearing and heading cosines
+        {
+            const double bx = g[0] - s[0], by = g[1] - s[1];
+            const double beta = (bx == 0.0 && by == 0.0) ? 0.0 : atan2(by, bx);
+            for (int h = tid; h < H; h += kPlanThreads) {
+                const double th = beta + 2.0 * M_PI * (double)h / (double)H;
+                sCos[h] = cos(th);
+                sSin[h] = sin(th);
+            }
+        }
+        const int row = t + 1;
+        const int n_row = row < tb.rows ? tb.rowN[row] : 0;
+        __syncthreads();
+
+        const float ch = sweeper ? (float)sCos[my_h] : 0.0f;
+        const float sh = sweeper ? (float)sSin[my_h] : 0.0f;
+        float acc[NC][NV];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[c][v] = INFINITY;
+
+        // 2-3. stage and sweep the row in tiles
+        const size_t rb = (size_t)row * tb.cap;
+        const int tcap = (kTile / (2 * n_slices)) * (2 * n_slices);   // whole sweep rounds per tile
+        for (int base = 0; base < n_row; base += tcap) {
+            const int nt = min(tcap, n_row - base);
+            const int npad = ((nt + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
+            for (int j = tid; j < npad; j += kPlanThreads) {
+                float4 e = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                if (j < nt) {
+                    const size_t idx = rb + base + j;
+                    const float qx = (float)((double)tb.X[idx] - s[0]);
+                    const float qy = (float)((double)tb.Y[idx] - s[1]);
+                    const float qz = (float)((double)tb.Z[idx] - s[2]);
+                    e.x = qx;
+                    e.y = qy;
+                    e.z = cfg.zeta_scale * qz;
+                    e.w = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+                }
+                tile[j] = e;
+            }
+            __syncthreads();
+            if (sweeper) {
+                for (int i = my_slice; i < npad; i += 2 * n_slices) {
+                    const float4 p0 = tile[i];
+                    const float4 p1 = tile[i + n_slices];
+                    const float hq0 = fmaf(p0.x, ch, p0.y * sh);
+                    const float hq1 = fmaf(p1.x, ch, p1.y * sh);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const float u0 = fmaf(kv[v], hq0, p0.w);
+                        const float u1 = fmaf(kv[v], hq1, p1.w);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            const float a0 = (c == ZC) ? u0 : fmaf(clf[c], p0.z, u0);
+                            const float a1 = (c == ZC) ? u1 : fmaf(clf[c], p1.z, u1);
+                            acc[c][v] = fminf(acc[c][v], fminf(a0, a1));
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // cross-slice reduction through LDS
+        float *red = reinterpret_cast<float *>(tile);
+        if (sweeper) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) red[my_slice * A + (my_h * NC + c) * NV + v] = acc[c][v];
+        }
+        __syncthreads();
+
+        // 4. per-action value
+        for (int a = tid; a < A; a += kPlanThreads) {
+            float m = INFINITY;
+            for (int sl = 0; sl < n_slices; ++sl) m = fminf(m, red[sl * A + a]);
+            const int h = a / (NC * NV);
+            const Scored r = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], m);
+            sV[a] = r.V;
+            sM[a] = m;
+            if (eval) {
+                if (ev.V) ev.V[a] = r.V;
+                if (ev.G) ev.G[a] = r.G;
+                if (ev.I) ev.I[a] = r.I;
+                if (ev.T) ev.T[a] = r.T;
+            }
+        }
+        __syncthreads();
+
+        // 5. argmax: largest value, then the lowest index within the tie band
+        double lv = -INFINITY;
+        for (int a = tid; a < A; a += kPlanThreads) lv = fmax(lv, sV[a]);
+        lv = wave_max(lv);
+        if (lane == 0) red_d[wave] = lv;
+        __syncthreads();
+        double vmax = red_d[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) vmax = fmax(vmax, red_d[w]);
+        const double thr = vmax - cfg.tie_rel * fabs(vmax);
+        int li = 0x7fffffff;
+        for (int a = tid; a < A; a += kPlanThreads)
+            if (sV[a] >= thr) { li = a; break; }
+        li = wave_min(li);
+        if (lane == 0) red_i[wave] = li;
+        __syncthreads();
+        int best = red_i[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) best = red_i[w] < best ? red_i[w] : best;
+        if (vmax == -INFINITY) best = -1;
+
+        pairs += (long long)A * n_row;
+        steps_here += 1;
+
+        if (eval) {
+            if (tid == 0 && ev.best) *ev.best = best;
+            break;
+        }
+
+        // 6. advance
+        if (tid == 0) {
+            if (best < 0) {
+                st_status = FASTMDP_NO_VALID_ACTION;
+            } else {
+                const int h = best / (NC * NV);
+                const Scored r = score_action(cfg, tb, best, s, g, sCos[h], sSin[h], sM[best]);
+                const size_t p = pt_base + n;
+                tr.xyz[p * 3 + 0] = r.x;
+                tr.xyz[p * 3 + 1] = r.y;
+                tr.xyz[p * 3 + 2] = r.z;
+                tr.act[p] = best;
+                tr.val[p] = r.V;
+                tr.seen[p] = n_row;
+                st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
+                st_n = n + 1;
+                if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
+                else if (r.clr < 0.0) st_status = FASTMDP_REJECT_TERRAIN;
+            }
+        }
+        __syncthreads();
+    }
+
+    __syncthreads();   // st_status written by thread 0 on the way out of the loop
+
+    // Commit validation of a finished OK trajectory against every table
+    // entry it saw: each point rounded to FP32 (the table's storage format)
+    // must be at least R_sep from every entry of its row that existed when
+    // the row was scored, and clear of the terrain.  Entries appended later
+    // are the sequencer's interaction check.
+    if (!eval && validate && st_status == FASTMDP_OK) {
+        const int n = st_n;
+        const double r2 = cfg.R_sep * cfg.R_sep;
+        int bad = 0;
+        for (int k = 0; k < n; ++k) {
+            const double *x = tr.xyz + (pt_base + k) * 3;
+            const double px = (float)x[0], py = (float)x[1], pz = (float)x[2];
+            const int lim = tr.seen[pt_base + k];
+            const size_t rb = (size_t)(t0 + k) * tb.cap;
+            for (int j = tid; j < lim; j += kPlanThreads) {
+                const double dx = (double)tb.X[rb + j] - px;
+                const double dy = (double)tb.Y[rb + j] - py;
+                const double dz = (double)tb.Z[rb + j] - pz;
+                if (dx * dx + dy * dy + dz * dz < r2) bad = 1;
+            }
+            if (tb.terr && (k % kPlanThreads) == tid && pz - terrain_height(tb, px, py) < 0.0) bad = 1;
+        }
+        if (tid == 0) st_flag = 0;
+        __syncthreads();
+        if (bad) st_flag = 1;     // benign race: every writer stores 1
+        __syncthreads();
+        if (tid == 0) S.valid = st_flag == 0;
+    }
+
+    if (tid == 0 && !eval) {
+        S.n_points = st_n;
+        S.status = st_status;
+    }
+    if (tid == 0) {
+        S.pairs += pairs;
+        S.steps += steps_here;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch dispatch over the supported (climbs, speeds, zero-climb) shapes
+// ---------------------------------------------------------------------------
+template <int NC, int NV, int ZC>
+static hipError_t launch_t(int nblk, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
+                           const int *list, const Traj &tr, int budget, int validate, const EvalOut &ev) {
+    hipLaunchKernelGGL((planner_kernel<NC, NV, ZC>), dim3(nblk), dim3(kPlanThreads), 0, st, c, t, s, list, tr,
+                       budget, validate, ev);
+    return hipGetLastError();
+}
+
+#define FMDP_SHAPE(NC, NV, ZC) \
+    if (c.n_climb == NC && c.n_speed == NV && zc == ZC) return launch_t<NC, NV, ZC>(nblk, st, c, t, s, list, tr, budget, validate, ev);
+
+hipError_t launch_planner(int nblk, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s, const int *list,
+                          const Traj &tr, int budget, int validate, const EvalOut &ev) {
+    const int zc = c.zero_climb;
+    FMDP_SHAPE(1, 1, 0) FMDP_SHAPE(1, 1, -1) FMDP_SHAPE(1, 2, 0) FMDP_SHAPE(1, 2, -1)
+    FMDP_SHAPE(1, 3, 0) FMDP_SHAPE(1, 3, -1)
+    FMDP_SHAPE(2, 1, -1) FMDP_SHAPE(2, 2, -1) FMDP_SHAPE(2, 3, -1)
+    FMDP_SHAPE(3, 1, 1) FMDP_SHAPE(3, 1, -1) FMDP_SHAPE(3, 2, 1) FMDP_SHAPE(3, 2, -1)
+    FMDP_SHAPE(3, 3, 1) FMDP_SHAPE(3, 3, -1)
+    FMDP_SHAPE(5, 1, 2) FMDP_SHAPE(5, 3, 2) FMDP_SHAPE(5, 3, -1)
+    return hipErrorInvalidValue;
+}
+
+bool planner_shape_supported(int n_climb, int n_speed, int zc) {
+    const int nc = n_climb, nv = n_speed;
+#define FMDP_OK(NC, NV, ZC) if (nc == NC && nv == NV && zc == ZC) return true;
+    FMDP_OK(1, 1, 0) FMDP_OK(1, 1, -1) FMDP_OK(1, 2, 0) FMDP_OK(1, 2, -1) FMDP_OK(1, 3, 0) FMDP_OK(1, 3, -1)
+    FMDP_OK(2, 1, -1) FMDP_OK(2, 2, -1) FMDP_OK(2, 3, -1)
+    FMDP_OK(3, 1, 1) FMDP_OK(3, 1, -1) FMDP_OK(3, 2, 1) FMDP_OK(3, 2, -1) FMDP_OK(3, 3, 1) FMDP_OK(3, 3, -1)
+    FMDP_OK(5, 1, 2) FMDP_OK(5, 3, 2) FMDP_OK(5, 3, -1)
+#undef FMDP_OK
+    return false;
+}
+
+}  // namespace fmdp

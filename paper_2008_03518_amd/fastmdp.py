@@ -1,0 +1,300 @@
+"""Python binding of libfastmdp (ctypes over the C ABI in include/fastmdp.h).
+
+Argument marshalling only: every step of the planner runs in the HIP
+kernels of the shared library.  Importing this module fails loudly when the
+library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfastmdp.so")
+MAX_ACT_DIM = 8
+TIE_REL = 1e-9
+
+E_INVAL, E_CAPACITY, E_DEVICE, E_CONFLICT, E_NOMEM, E_IO = -1, -2, -3, -4, -5, -6
+OK, REJECT_SEPARATION, REJECT_TERRAIN, REJECT_ORIGIN, TIMEOUT, NO_VALID_ACTION = 0, 1, 2, 3, 4, 5
+
+
+class FastMDPError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn}: {msg} ({code})")
+        self.code = code
+
+
+class _Vec3(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("z", C.c_double)]
+
+
+class _Config(C.Structure):
+    _fields_ = [
+        ("box_min", C.c_double * 3), ("box_max", C.c_double * 3),
+        ("dt", C.c_double),
+        ("gamma", C.c_double), ("r_goal", C.c_double),
+        ("r_intr", C.c_double), ("R_intr", C.c_double), ("gamma_intr", C.c_double),
+        ("R_sep", C.c_double),
+        ("r_terr", C.c_double), ("R_terr", C.c_double), ("gamma_terr", C.c_double),
+        ("n_head", C.c_int32), ("n_climb", C.c_int32), ("n_speed", C.c_int32),
+        ("climb", C.c_double * MAX_ACT_DIM), ("speed", C.c_double * MAX_ACT_DIM),
+        ("max_steps", C.c_int32), ("plan_capacity", C.c_int32), ("max_rows", C.c_int32),
+        ("max_slots", C.c_int32),
+        ("tie_rel", C.c_double),
+    ]
+
+
+class _Request(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("origin", _Vec3), ("goal", _Vec3), ("t0", C.c_int32)]
+
+
+class _Plan(C.Structure):
+    _fields_ = [("status", C.c_int32), ("t0", C.c_int32), ("n_points", C.c_int32), ("capacity", C.c_int32),
+                ("xyz", C.POINTER(C.c_double)), ("action", C.POINTER(C.c_int32)), ("value", C.POINTER(C.c_double))]
+
+
+class _State(C.Structure):
+    _fields_ = [("pos", _Vec3), ("goal", _Vec3), ("t", C.c_int32)]
+
+
+def _load_lib():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfastmdp.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    dp, ip, fp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_float)
+    lib.fastmdp_create.argtypes = [C.POINTER(_Config), C.POINTER(P)]
+    lib.fastmdp_destroy.argtypes = [P]
+    lib.fastmdp_destroy.restype = None
+    lib.fastmdp_set_stream.argtypes = [P, P]
+    lib.fastmdp_load_plans.argtypes = [P, I32, ip, ip, fp]
+    lib.fastmdp_set_terrain.argtypes = [P, I32, I32, fp, D, D, D]
+    lib.fastmdp_eval_step.argtypes = [P, C.POINTER(_State), dp, dp, dp, dp, ip]
+    lib.fastmdp_plan_request.argtypes = [P, C.POINTER(_Request), C.POINTER(_Plan)]
+    lib.fastmdp_commit_plan.argtypes = [P, C.POINTER(_Plan)]
+    lib.fastmdp_num_plans.argtypes = [P]
+    lib.fastmdp_plan_fcfs.argtypes = [P, I32, C.POINTER(_Request), C.POINTER(_Plan), ip]
+    lib.fastmdp_last_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64),
+                                       C.POINTER(D)]
+    lib.fastmdp_save_table.argtypes = [P, C.c_char_p]
+    lib.fastmdp_load_table.argtypes = [P, C.c_char_p]
+    lib.fastmdp_strerror.argtypes = [C.c_int]
+    lib.fastmdp_strerror.restype = C.c_char_p
+    return lib
+
+
+_lib = _load_lib()
+
+EXPORTS = [
+    "fastmdp_create", "fastmdp_destroy", "fastmdp_set_stream", "fastmdp_load_plans", "fastmdp_set_terrain",
+    "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_commit_plan", "fastmdp_num_plans", "fastmdp_plan_fcfs",
+    "fastmdp_last_stats", "fastmdp_save_table", "fastmdp_load_table", "fastmdp_strerror",
+]
+
+
+def strerror(code: int) -> str:
+    return _lib.fastmdp_strerror(int(code)).decode()
+
+
+def _check(fn: str, rc: int) -> int:
+    if rc < 0:
+        raise FastMDPError(fn, rc, strerror(rc))
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL) -> _Config:
+    c = _Config()
+    for k in range(3):
+        c.box_min[k] = float(cfg.box_min[k])
+        c.box_max[k] = float(cfg.box_max[k])
+    for name in ("dt", "gamma", "r_goal", "r_intr", "R_intr", "gamma_intr", "R_sep", "r_terr", "R_terr",
+                 "gamma_terr"):
+        setattr(c, name, float(getattr(cfg, name)))
+    c.n_head = int(cfg.n_head)
+    c.n_climb = len(cfg.climb)
+    c.n_speed = len(cfg.speed)
+    for i, v in enumerate(cfg.climb):
+        c.climb[i] = float(v)
+    for i, v in enumerate(cfg.speed):
+        c.speed[i] = float(v)
+    c.max_steps = int(cfg.max_steps)
+    c.plan_capacity = int(cfg.plan_capacity)
+    c.max_rows = int(cfg.max_rows)
+    c.max_slots = int(max_slots)
+    c.tie_rel = float(tie_rel)
+    return c
+
+
+class Plan:
+    """A trajectory returned by the planner (host arrays)."""
+
+    def __init__(self, capacity: int):
+        self.xyz = np.zeros((capacity, 3))
+        self.action = np.zeros(capacity, dtype=np.int32)
+        self.value = np.zeros(capacity)
+        self.c = _Plan(0, 0, 0, capacity, _dptr(self.xyz), _iptr(self.action), _dptr(self.value))
+
+    @property
+    def status(self) -> int:
+        return int(self.c.status)
+
+    @property
+    def t0(self) -> int:
+        return int(self.c.t0)
+
+    @property
+    def n_points(self) -> int:
+        return int(self.c.n_points)
+
+    def points(self) -> np.ndarray:
+        return self.xyz[: self.n_points]
+
+    def actions(self) -> np.ndarray:
+        return self.action[: self.n_points]
+
+    def values(self) -> np.ndarray:
+        return self.value[: self.n_points]
+
+
+def _request(origin, goal, t0: int, ident: int = 0) -> _Request:
+    r = _Request()
+    r.id = int(ident)
+    r.origin = _Vec3(*[float(v) for v in origin])
+    r.goal = _Vec3(*[float(v) for v in goal])
+    r.t0 = int(t0)
+    return r
+
+
+class Context:
+    """One planner context on the current HIP device."""
+
+    def __init__(self, cfg, max_slots: int = 1, tie_rel: float = TIE_REL):
+        self.cfg = cfg
+        self._c = make_config(cfg, max_slots, tie_rel)
+        self.A = int(cfg.n_head) * len(cfg.climb) * len(cfg.speed)
+        self.capacity = int(cfg.max_steps) + 1
+        h = C.c_void_p()
+        _check("fastmdp_create", _lib.fastmdp_create(C.byref(self._c), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fastmdp_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_handle: Optional[int]):
+        _check("fastmdp_set_stream", _lib.fastmdp_set_stream(self._h, C.c_void_p(stream_handle or 0)))
+
+    def load_plans(self, plans) -> None:
+        t0 = np.ascontiguousarray(plans.t0, dtype=np.int32)
+        ln = np.ascontiguousarray(plans.length, dtype=np.int32)
+        xyz = np.ascontiguousarray(plans.xyz, dtype=np.float32)
+        _check("fastmdp_load_plans", _lib.fastmdp_load_plans(self._h, int(t0.shape[0]), _iptr(t0), _iptr(ln), _fptr(xyz)))
+
+    def set_terrain(self, terrain) -> None:
+        h = np.ascontiguousarray(terrain.h, dtype=np.float32)
+        _check("fastmdp_set_terrain", _lib.fastmdp_set_terrain(self._h, int(terrain.nx), int(terrain.ny), _fptr(h),
+                                                               float(terrain.x0), float(terrain.y0),
+                                                               float(terrain.cell)))
+
+    @property
+    def n_plans(self) -> int:
+        return _check("fastmdp_num_plans", _lib.fastmdp_num_plans(self._h))
+
+    def eval_step(self, s, g, t: int) -> dict:
+        st = _State(_Vec3(*[float(v) for v in s]), _Vec3(*[float(v) for v in g]), int(t))
+        A = self.A
+        V, G, I, T = (np.zeros(A) for _ in range(4))
+        best = np.zeros(1, dtype=np.int32)
+        _check("fastmdp_eval_step", _lib.fastmdp_eval_step(self._h, C.byref(st), _dptr(V), _dptr(G), _dptr(I),
+                                                           _dptr(T), _iptr(best)))
+        return dict(V=V, G=G, I=I, T=T, best=int(best[0]))
+
+    def plan_request(self, origin, goal, t0: int = 0, ident: int = 0) -> Plan:
+        p = Plan(self.capacity)
+        r = _request(origin, goal, t0, ident)
+        _check("fastmdp_plan_request", _lib.fastmdp_plan_request(self._h, C.byref(r), C.byref(p.c)))
+        return p
+
+    def commit_plan(self, plan: Plan) -> bool:
+        """True if appended; False if refused for a separation/terrain conflict."""
+        rc = _lib.fastmdp_commit_plan(self._h, C.byref(plan.c))
+        if rc == E_CONFLICT:
+            return False
+        _check("fastmdp_commit_plan", rc)
+        return True
+
+    def commit_points(self, t0: int, xyz) -> bool:
+        """Commit an arbitrary FP64 trajectory (status OK) -- for tests and tools."""
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        p = Plan(xyz.shape[0])
+        p.xyz[:] = xyz
+        p.c.status, p.c.t0, p.c.n_points = OK, int(t0), xyz.shape[0]
+        return self.commit_plan(p)
+
+    def plan_fcfs(self, requests, limit: Optional[int] = None):
+        """Plan requests first-come-first-served with concurrent slots.
+
+        Returns (plans, committed) with committed a bool array.
+        """
+        m = requests.n if limit is None else min(limit, requests.n)
+        arr = (_Request * max(m, 1))()
+        for k in range(m):
+            arr[k] = _request(requests.origin[k], requests.goal[k], int(requests.t0[k]), int(requests.ident[k]))
+        plans = [Plan(self.capacity) for _ in range(m)]
+        parr = (_Plan * max(m, 1))()
+        for k in range(m):
+            parr[k] = plans[k].c
+        committed = np.zeros(max(m, 1), dtype=np.int32)
+        _check("fastmdp_plan_fcfs", _lib.fastmdp_plan_fcfs(self._h, m, arr, parr, _iptr(committed)))
+        for k in range(m):
+            plans[k].c = parr[k]
+        return plans, committed[:m].astype(bool)
+
+    def stats(self) -> dict:
+        v = [C.c_int64() for _ in range(4)]
+        ms = C.c_double()
+        _check("fastmdp_last_stats", _lib.fastmdp_last_stats(self._h, *[C.byref(x) for x in v], C.byref(ms)))
+        return dict(pairs=v[0].value, steps=v[1].value, resumes=v[2].value, launches=v[3].value, kernel_ms=ms.value)
+
+    def save_table(self, path: str) -> None:
+        _check("fastmdp_save_table", _lib.fastmdp_save_table(self._h, path.encode()))
+
+    def load_table(self, path: str) -> None:
+        _check("fastmdp_load_table", _lib.fastmdp_load_table(self._h, path.encode()))
+
+
+def context_for(scenario, max_slots: int = 1) -> Context:
+    """Context with the scenario's known plans and terrain loaded."""
+    ctx = Context(scenario.cfg, max_slots=max_slots)
+    ctx.load_plans(scenario.plans)
+    if scenario.terrain is not None:
+        ctx.set_terrain(scenario.terrain)
+    return ctx

@@ -1,0 +1,286 @@
+"""HIP planner versus the FP64 oracle, through the C ABI.
+
+Sizes: the 50/200-plan 10 km box (81 actions), the paper-scale 2000-plan box
+with terrain (81 actions), and the 3000-plan, 360-action workload at full
+size on sampled requests; plus ragged multi-tile rows, outcomes, commit,
+checkpoint and the first-come-first-served batch against sequential
+planning.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from parity import compare_eval, compare_trajectory  # noqa: E402
+
+from oracle.oracle import Oracle  # noqa: E402
+from paper_2008_03518_amd import scenario as S  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fm():
+    from paper_2008_03518_amd import fastmdp
+    return fastmdp
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _states_near_plans(sc, n, seed):
+    rng = np.random.default_rng(seed)
+    off = sc.plans.offsets()
+    out = []
+    while len(out) < n:
+        j = int(rng.integers(sc.plans.n))
+        L = int(sc.plans.length[j])
+        if L < 3:
+            continue
+        k = int(rng.integers(0, L - 1))
+        p = sc.plans.xyz[off[j] + k + 1].astype(np.float64)
+        s = p + rng.uniform(-170, 170, 3) * np.array([1.0, 1.0, 0.4])
+        lo, hi = np.array(sc.cfg.box_min), np.array(sc.cfg.box_max)
+        s = np.clip(s, lo + 1.0, hi - 1.0)
+        g = np.array([rng.uniform(lo[0], hi[0]), rng.uniform(lo[1], hi[1]), rng.uniform(100, 900)])
+        out.append((s, g, int(sc.plans.t0[j]) + k))
+    return out
+
+
+# ---------------------------------------------------------------------------
+def test_eval_step_small_near_plans(fm):
+    sc = S.small(seed=0, n_plans=200, n_requests=1)
+    orc = Oracle(sc.cfg, sc.plans)
+    n_cmp = n_in = 0
+    with fm.context_for(sc) as ctx:
+        for s, g, t in _states_near_plans(sc, 80, 11):
+            o = orc.eval_step(s, g, t)
+            r = ctx.eval_step(s, g, t)
+            n, _, mx, _, _ = compare_eval(r, o)
+            n_cmp += n
+            n_in += int(np.sum(o["I"] > 0))
+    _log(f"[eval small] compared {n_cmp} actions, {n_in} inside wells")
+    assert n_in > 200
+
+
+def test_eval_step_small_teacher_forced(fm):
+    sc = S.small(seed=0, n_plans=200, n_requests=3)
+    orc = Oracle(sc.cfg, sc.plans)
+    with fm.context_for(sc) as ctx:
+        for q in range(sc.requests.n):
+            op = orc.plan(sc.requests.origin[q], sc.requests.goal[q], 0)
+            for k in range(op.n_points - 1):
+                o = orc.eval_step(op.xyz[k], sc.requests.goal[q], k)
+                r = ctx.eval_step(op.xyz[k], sc.requests.goal[q], k)
+                compare_eval(r, o)
+            _log(f"[teacher small] request {q}: {op.n_points - 1} steps ok (status {op.status})")
+
+
+def test_plan_request_small(fm):
+    sc = S.small(seed=4, n_plans=200, n_requests=6)
+    orc = Oracle(sc.cfg, sc.plans)
+    with fm.context_for(sc) as ctx:
+        for q in range(sc.requests.n):
+            op = orc.plan(sc.requests.origin[q], sc.requests.goal[q], 0)
+            gp = ctx.plan_request(sc.requests.origin[q], sc.requests.goal[q], 0)
+            same, diverged = compare_trajectory(gp, op, orc, sc.requests.goal[q])
+            _log(f"[plan small] request {q}: {same} identical points, diverged={diverged}, status {op.status}")
+
+
+def _fcfs_sync(fm, sc, n_req, teacher_every=0):
+    """Plan requests in order on both sides; commit each plan to both tables.
+
+    While the GPU and oracle trajectories are identical the GPU commits its
+    own plan; after an excused divergence both tables receive the oracle's
+    plan, so that the next request starts from identical tables.
+    """
+    orc = Oracle(sc.cfg, sc.plans, sc.terrain)
+    stats = dict(identical=0, diverged=0, committed=0)
+    with fm.context_for(sc) as ctx:
+        for q in range(n_req):
+            goal = sc.requests.goal[q]
+            op = orc.plan(sc.requests.origin[q], goal, int(sc.requests.t0[q]))
+            gp = ctx.plan_request(sc.requests.origin[q], goal, int(sc.requests.t0[q]))
+            same, diverged = compare_trajectory(gp, op, orc, goal)
+            if teacher_every:
+                for k in range(0, op.n_points - 1, teacher_every):
+                    compare_eval(ctx.eval_step(op.xyz[k], goal, op.t0 + k), orc.eval_step(op.xyz[k], goal, op.t0 + k))
+            ok_o = orc.commit(op) if op.status == 0 else False
+            if op.status == 0:
+                if diverged:
+                    ok_g = ctx.commit_points(op.t0, op.xyz)
+                else:
+                    ok_g = ctx.commit_plan(gp)
+                assert ok_g == ok_o
+            assert ctx.n_plans == orc.n_plans
+            stats["diverged" if diverged else "identical"] += 1
+            stats["committed"] += int(ok_o)
+            _log(f"[fcfs sync] request {q}: status {op.status}, {op.n_points} points, "
+                 f"identical {same}, diverged {diverged}")
+    return stats
+
+
+def test_fcfs_sync_small(fm):
+    st = _fcfs_sync(fm, S.small(seed=5, n_plans=120, n_requests=12), 12, teacher_every=5)
+    _log(f"[fcfs small] {st}")
+    assert st["committed"] >= 6
+
+
+def test_paper_scale_terrain(fm):
+    sc = S.paper_scale(seed=1, n_plans=2000, n_requests=200)
+    st = _fcfs_sync(fm, sc, 6, teacher_every=25)
+    _log(f"[paper scale] {st}")
+
+
+def test_large_actions_full_size_sampled(fm):
+    sc = S.large_actions(seed=2, n_plans=3000, n_requests=1000)
+    st = _fcfs_sync(fm, sc, 2, teacher_every=40)
+    _log(f"[3000 plans x 360 actions] {st}")
+
+
+def test_multi_tile_ragged_rows(fm):
+    """Rows far larger than one LDS tile, with a ragged tail."""
+    cfg = S.cfg_large_actions()
+    cfg.plan_capacity = 6000
+    rng = np.random.default_rng(9)
+    n = 5000 + 37
+    s = np.array([15000.0, 15000.0, 700.0])
+    pts = s[None, :] + rng.uniform(-2000, 2000, (n, 3)) * np.array([1, 1, 0.15])
+    pts[:50] = s[None, :] + rng.uniform(-170, 170, (50, 3))
+    L = 8
+    plans = S.Plans(t0=np.zeros(n, np.int32), length=np.full(n, L, np.int32),
+                    xyz=np.repeat(pts[:, None, :], L, axis=1).reshape(-1, 3).astype(np.float32))
+    orc = Oracle(cfg, plans)
+    with fm.Context(cfg) as ctx:
+        ctx.load_plans(plans)
+        for q, g in enumerate([np.array([29000.0, 15000.0, 700.0]), np.array([100.0, 29000.0, 300.0])]):
+            for t in range(3):
+                o = orc.eval_step(s + [3.0 * t, -2.0 * t, 1.0], g, t)
+                r = ctx.eval_step(s + [3.0 * t, -2.0 * t, 1.0], g, t)
+                compare_eval(r, o)
+        st = ctx.stats()
+        assert st["pairs"] == cfg.n_actions * n
+
+
+def test_empty_table_straight_track(fm):
+    cfg = S.cfg_large_actions()
+    o, g = np.array([1000.0, 5000.0, 300.0]), np.array([9030.0, 5000.0, 300.0])
+    with fm.Context(cfg) as ctx:
+        p = ctx.plan_request(o, g, 0)
+    D = 8030.0
+    assert p.status == 0 and p.n_points - 1 == int(np.ceil(D / cfg.ell - 1.0))
+    assert np.max(np.abs(p.points()[:, 1] - 5000.0)) < 1e-6 and np.max(np.abs(p.points()[:, 2] - 300.0)) < 1e-9
+
+
+def test_outcomes(fm):
+    cfg = S.cfg_small()
+    o = np.array([5000.0, 5000.0, 500.0])
+    goal = np.array([9000.0, 5000.0, 500.0])
+    # every successor inside a well
+    x = np.repeat(o[None, :], 64, axis=0)
+    x[0] += [0.0, 0.0, 400.0]
+    with fm.Context(cfg) as ctx:
+        ctx.load_plans(S.Plans(np.zeros(1, np.int32), np.array([64], np.int32), x.astype(np.float32)))
+        p = ctx.plan_request(o, goal, 0)
+        assert p.status == fm.REJECT_SEPARATION and p.n_points == 2
+        p = ctx.plan_request(o, goal, 1)        # the plan sits on the origin at row 1
+        assert p.status == fm.REJECT_ORIGIN and p.n_points == 1
+    c2 = S.cfg_small()
+    c2.max_steps = 5
+    with fm.Context(c2) as ctx:
+        p = ctx.plan_request([1000.0, 1000.0, 500.0], [9000.0, 9000.0, 500.0], 0)
+        assert p.status == fm.TIMEOUT and p.n_points == 6
+    tiny = S.cfg_small()
+    tiny.box_min, tiny.box_max = (0.0, 0.0, 0.0), (10.0, 10.0, 1000.0)
+    with fm.Context(tiny) as ctx:
+        p = ctx.plan_request([5.0, 5.0, 500.0], [9.0, 9.0, 900.0], 0)
+        assert p.status == fm.NO_VALID_ACTION and p.n_points == 1
+    c3 = S.cfg_small()
+    c3.climb = (-5.0,)
+    xs = np.arange(17) * 625.0
+    X, Y = np.meshgrid(xs, xs)
+    ter = S.Terrain(17, 17, np.full(X.shape, 497.0, np.float32), 0.0, 0.0, 625.0, np.zeros((0, 4)))
+    with fm.Context(c3) as ctx:
+        ctx.set_terrain(ter)
+        p = ctx.plan_request(o, goal, 0)
+        assert p.status == fm.REJECT_TERRAIN and p.n_points == 2
+
+
+def test_commit_validates_and_appends(fm):
+    cfg = S.cfg_small()
+    base = np.repeat(np.array([[5000.0, 5000.0, 500.0]], np.float32), 30, axis=0)
+    with fm.Context(cfg) as ctx:
+        ctx.load_plans(S.Plans(np.zeros(1, np.int32), np.array([30], np.int32), base))
+        near = np.repeat(np.array([[5100.0, 5000.0, 500.0]]), 10, axis=0)
+        assert ctx.commit_points(5, near) is False and ctx.n_plans == 1
+        assert ctx.commit_points(31, near) is True and ctx.n_plans == 2
+        far = np.repeat(np.array([[5151.0, 5000.0, 500.0]]), 10, axis=0)
+        assert ctx.commit_points(0, far) is True and ctx.n_plans == 3
+        assert ctx.commit_points(28, far) is False and ctx.n_plans == 3
+        far2 = np.repeat(np.array([[5000.0, 5000.0, 650.5]]), 10, axis=0)
+        assert ctx.commit_points(60, far2) is True and ctx.n_plans == 4
+        assert ctx.commit_points(0, far2 - [0.0, 0.0, 1.0]) is False
+        with pytest.raises(fm.FastMDPError):
+            ctx.commit_points(cfg.max_rows - 3, near)          # runs past the last row
+
+
+def test_checkpoint_roundtrip(fm, tmp_path):
+    sc = S.small(seed=6, n_plans=100, n_requests=3)
+    path = str(tmp_path / "table.bin")
+    with fm.context_for(sc) as ctx:
+        p0 = ctx.plan_request(sc.requests.origin[0], sc.requests.goal[0], 0)
+        assert p0.status == 0 and ctx.commit_plan(p0)
+        ctx.save_table(path)
+        p1 = ctx.plan_request(sc.requests.origin[1], sc.requests.goal[1], 0)
+    with fm.Context(sc.cfg) as ctx2:
+        ctx2.load_table(path)
+        assert ctx2.n_plans == sc.plans.n + 1
+        p2 = ctx2.plan_request(sc.requests.origin[1], sc.requests.goal[1], 0)
+    assert p1.n_points == p2.n_points and np.array_equal(p1.points(), p2.points())
+
+
+def test_determinism(fm):
+    sc = S.large_actions(seed=8, n_plans=600, n_requests=2)
+    with fm.context_for(sc) as ctx:
+        a = ctx.plan_request(sc.requests.origin[0], sc.requests.goal[0], 0)
+        b = ctx.plan_request(sc.requests.origin[0], sc.requests.goal[0], 0)
+    assert a.n_points == b.n_points and np.array_equal(a.points(), b.points()) and np.array_equal(a.values(), b.values())
+
+
+def _separation_violations(sc, plans, committed):
+    off = sc.plans.offsets()
+    tabs = [(int(sc.plans.t0[j]), sc.plans.xyz[off[j]:off[j + 1]].astype(np.float64)) for j in range(sc.plans.n)]
+    bad = 0
+    mine = [(p.t0, p.points().astype(np.float32).astype(np.float64)) for p, c in zip(plans, committed) if c]
+    for i, (ti, xi) in enumerate(mine):
+        for tj, xj in tabs + mine[:i]:
+            lo, hi = max(ti, tj), min(ti + len(xi), tj + len(xj))
+            if lo < hi and np.min(np.linalg.norm(xi[lo - ti:hi - ti] - xj[lo - tj:hi - tj], axis=1)) < sc.cfg.R_sep:
+                bad += 1
+    return bad
+
+
+def test_fcfs_batch_equals_sequential(fm):
+    """Alone versus in the mix: concurrent FCFS gives bitwise the sequential result."""
+    sc = S.large_actions(seed=12, n_plans=400, n_requests=48)
+    cfg = sc.cfg
+    seq = []
+    with fm.context_for(sc) as ctx:
+        for q in range(sc.requests.n):
+            p = ctx.plan_request(sc.requests.origin[q], sc.requests.goal[q], 0)
+            c = ctx.commit_plan(p) if p.status == 0 else False
+            seq.append((p, c))
+    with fm.context_for(sc, max_slots=16) as ctx:
+        plans, committed = ctx.plan_fcfs(sc.requests)
+        st = ctx.stats()
+    _log(f"[fcfs batch] stats {st}")
+    for q, ((p, c), b, cb) in enumerate(zip(seq, plans, committed)):
+        assert p.status == b.status and p.n_points == b.n_points, q
+        assert np.array_equal(p.points(), b.points()) and np.array_equal(p.actions(), b.actions()), q
+        assert np.array_equal(p.values(), b.values()), q
+        assert c == cb, q
+    assert _separation_violations(sc, plans, committed) == 0
+    assert committed.sum() >= sc.requests.n // 2
