@@ -82,6 +82,8 @@ typedef struct {
     int32_t plan_capacity;           /* known-plan entries per time row           */
     int32_t max_rows;                /* time rows in the table                    */
     int32_t max_slots;               /* requests planned concurrently (>= 1)      */
+    int32_t steps_per_launch;        /* FCFS engine: steps per slot between
+                                        acceptance passes (0: 256)                */
     double tie_rel;                  /* argmax: values within tie_rel*|max| of the
                                         maximum tie; the lowest index wins        */
 } fastmdp_config;
@@ -169,19 +171,30 @@ int fastmdp_commit_plan(fastmdp_ctx *ctx, const fastmdp_plan *plan);
 /* Number of plans in the table (loaded plus committed). */
 int fastmdp_num_plans(const fastmdp_ctx *ctx);
 
-/* First-come-first-served batch (Sec. V; "independent parallel instances"
- * of the method generalised to overlapping requests).  Requests are planned
- * concurrently in up to max_slots slots against the table as it stands;
- * then, strictly in request order, each finished trajectory is checked
- * against the plans committed after it was planned: if no committed point
- * lies within reach of any scored successor, the trajectory is the one a
- * sequential plan-then-commit would produce and it is accepted (committed
- * when status is OK); otherwise planning resumes from the first affected
- * step.  plans[i] receives request i's trajectory (caller buffers as for
- * fastmdp_plan_request); committed[i] is 1 if it entered the table.
+/* First-come-first-served planning of a request stream (Sec. V; the
+ * paper's "independent parallel instances" generalised to overlapping
+ * requests).  Requests are admitted in order into up to max_slots slots --
+ * request i not before arrival_s[i] seconds after the call starts (NULL: all
+ * at once) -- and planned concurrently against the table as it stands.  Then,
+ * strictly in request order, each finished trajectory is checked against
+ * the plans committed after it scored their rows: if no committed point lies
+ * within reach of a scored successor, the trajectory is the one a
+ * sequential plan-then-commit would produce and it is accepted (appended
+ * when its status is OK, after the commit validation); otherwise planning
+ * resumes from the first affected step.  plans[i] receives request i's
+ * trajectory (caller buffers as for fastmdp_plan_request); committed[i] is 1
+ * if it entered the table; done_s[i] (may be NULL) is the time, in seconds
+ * since the call started, at which request i was accepted or rejected.
  * Errors: E_INVAL, E_CAPACITY, E_DEVICE. */
-int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs,
-                      fastmdp_plan *plans, int32_t *committed);
+int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, const double *arrival_s,
+                      fastmdp_plan *plans, int32_t *committed, double *done_s);
+
+/* Remember the table's current extent / drop every plan appended since the
+ * last snapshot (row counts return to the snapshot; nothing is copied).
+ * Rewinding without a snapshot empties the table.  For re-running a batch
+ * against the same accepted plans, or discarding tentative commits. */
+int fastmdp_table_snapshot(fastmdp_ctx *ctx);
+int fastmdp_table_rewind(fastmdp_ctx *ctx);
 
 /* Counters of the last fastmdp_plan_request / fastmdp_plan_fcfs /
  * fastmdp_eval_step call: pair evaluations (action x active plan per step),

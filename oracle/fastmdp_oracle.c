@@ -12,6 +12,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t t0, n;
@@ -58,6 +61,14 @@ void orc_destroy(orc_world *w) {
 }
 
 int orc_num_plans(const orc_world *w) { return w ? w->n_plans : ORC_E_INVAL; }
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int orc_add_plan(orc_world *w, int32_t t0, int32_t n, const float *xyz) {
     if (!w || n < 1 || t0 < 0 || !xyz) return ORC_E_INVAL;
@@ -283,8 +294,9 @@ int orc_commit(orc_world *w, int32_t t0, int32_t n, const double *xyz) {
     float *f = (float *)malloc((size_t)n * 3 * sizeof(float));
     if (!f) return ORC_E_NOMEM;
     for (int32_t k = 0; k < 3 * n; ++k) f[k] = (float)xyz[k];
+    /* the trajectory as planned is checked against the plans as stored */
     for (int32_t k = 0; k < n; ++k) {
-        double x[3] = {(double)f[3 * k], (double)f[3 * k + 1], (double)f[3 * k + 2]};
+        const double *x = xyz + 3 * k;
         for (int j = 0; j < w->n_plans; ++j) {
             double q[3];
             if (plan_point(&w->plans[j], t0 + k, q) && dist3(x, q) < c->R_sep) {

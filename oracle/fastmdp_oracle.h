@@ -87,6 +87,8 @@ void orc_destroy(orc_world *w);
 /* Append a plan without validation (known plans loaded from the database). */
 int  orc_add_plan(orc_world *w, int32_t t0, int32_t n, const float *xyz);
 int  orc_num_plans(const orc_world *w);
+/* Threads the per-action loop of orc_eval_step may use (OpenMP). */
+int  orc_num_threads(void);
 
 /* Heightmap h[j*nx+i] at (x0 + i*cell, y0 + j*cell); bilinear, clamped. */
 int  orc_set_terrain(orc_world *w, int32_t nx, int32_t ny, const float *h,
@@ -108,9 +110,9 @@ int  orc_plan(const orc_world *w, const double origin[3], const double goal[3], 
               int32_t cap, double *xyz, int32_t *act, double *val,
               int32_t *n_pts, int32_t *status);
 
-/* Validate a trajectory (rounded to FP32, the table's storage format)
- * against every plan in the table and the terrain; append it if clear.
- * Returns 0, or ORC_E_CONFLICT with the table unchanged. */
+/* Validate a trajectory as planned (FP64) against every plan in the table
+ * as stored (FP32) and against the terrain; if clear, append it rounded to
+ * FP32.  Returns 0, or ORC_E_CONFLICT with the table unchanged. */
 int  orc_commit(orc_world *w, int32_t t0, int32_t n, const double *xyz);
 
 #ifdef __cplusplus

@@ -71,6 +71,7 @@ def _load():
         lib.orc_eval_step.argtypes = [P, dp, dp, C.c_int32, dp, dp, dp, dp, dp, ip, ip]
         lib.orc_plan.argtypes = [P, dp, dp, C.c_int32, C.c_int32, dp, ip, dp, ip, ip]
         lib.orc_commit.argtypes = [P, C.c_int32, C.c_int32, dp]
+        lib.orc_num_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -231,6 +232,11 @@ def run_fcfs(oracle: Oracle, requests, limit: Optional[int] = None, commit: bool
             committed = oracle.commit(p)
         out.append((p, committed))
     return out
+
+
+def num_threads() -> int:
+    """Threads the oracle's per-action loop uses."""
+    return int(_load().orc_num_threads())
 
 
 def action_index(cfg, h: int, c: int, v: int) -> int:

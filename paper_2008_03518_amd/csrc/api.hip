@@ -7,7 +7,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -31,6 +33,8 @@ struct fastmdp_ctx {
     hipStream_t own = nullptr, stream = nullptr;
     std::vector<int> hRowN;
     int n_plans = 0;
+    std::vector<int> snapRowN;            // table snapshot (row counts)
+    int snap_plans = 0;
     float *dTerr = nullptr;
     int max_slots = 1, stride = 0;
     Slot *dSlots = nullptr;
@@ -38,7 +42,7 @@ struct fastmdp_ctx {
     Traj tr{};
     double *dEv = nullptr;        // 4*A eval outputs
     int *dBest = nullptr;
-    float *dPts = nullptr;        // stride*3 commit staging
+    double *dPts = nullptr;       // stride*3 commit staging (FP64 trajectory)
     int *dFlag = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::mutex mu;
@@ -372,9 +376,7 @@ int fastmdp_commit_plan(fastmdp_ctx *ctx, const fastmdp_plan *plan) {
     if ((long)t0 + n > ctx->tb.rows || n > ctx->stride) return FASTMDP_E_CAPACITY;
     for (int k = 0; k < n; ++k)
         if (ctx->hRowN[t0 + k] >= ctx->tb.cap) return FASTMDP_E_CAPACITY;
-    std::vector<float> pts((size_t)n * 3);
-    for (size_t i = 0; i < pts.size(); ++i) pts[i] = (float)plan->xyz[i];
-    HIP_TRY(hipMemcpyAsync(ctx->dPts, pts.data(), pts.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->dPts, plan->xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(fmdp::launch_fill_int(ctx->dFlag, 0, 1, ctx->stream));
     HIP_TRY(fmdp::launch_commit_check(ctx->dc, ctx->tb, ctx->dPts, t0, n, ctx->dFlag, ctx->stream));
     HIP_TRY(fmdp::launch_commit_append(ctx->tb, ctx->dPts, t0, n, ctx->dFlag, ctx->stream));
@@ -390,28 +392,34 @@ int fastmdp_commit_plan(fastmdp_ctx *ctx, const fastmdp_plan *plan) {
 
 int fastmdp_num_plans(const fastmdp_ctx *ctx) { return ctx ? ctx->n_plans : FASTMDP_E_INVAL; }
 
-int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, fastmdp_plan *plans,
-                      int32_t *committed) {
+int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, const double *arrival_s,
+                      fastmdp_plan *plans, int32_t *committed, double *done_s) {
     if (!ctx || n < 0 || (n > 0 && (!reqs || !plans || !committed))) return FASTMDP_E_INVAL;
     for (int i = 0; i < n; ++i) {
         if (reqs[i].t0 < 0) return FASTMDP_E_INVAL;
+        if (arrival_s && (i > 0 && arrival_s[i] < arrival_s[i - 1])) return FASTMDP_E_INVAL;
         if (plans[i].capacity < ctx->stride || !plans[i].xyz || !plans[i].action || !plans[i].value)
             return FASTMDP_E_CAPACITY;
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
     reset_stats(ctx);
+    using clk = std::chrono::steady_clock;
+    const auto t_start = clk::now();
+    auto now_s = [&]() { return std::chrono::duration<double>(clk::now() - t_start).count(); };
     const int S = std::min(ctx->max_slots, std::max(n, 1));
-    const int budget = 256;
+    const int budget = ctx->cfg.steps_per_launch > 0 ? ctx->cfg.steps_per_launch : 256;
     std::vector<Slot> hs(S);
     std::vector<int> slot_req(S, -1);        // request held by each slot
     std::vector<int> req_slot(n, -1);
     int next_req = 0, next_commit = 0;
     std::vector<int> list, order;
     while (next_commit < n) {
-        // admit requests into free slots (in request order)
+        // admit arrived requests into free slots, in request order
         bool dirty = false;
+        const double t_now = arrival_s ? now_s() : 0.0;
         for (int s = 0; s < S && next_req < n; ++s)
             if (slot_req[s] < 0) {
+                if (arrival_s && arrival_s[next_req] > t_now) break;
                 hs[s] = fresh_slot(reqs[next_req], next_req);
                 slot_req[s] = next_req;
                 req_slot[next_req] = s;
@@ -423,6 +431,12 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
         list.clear();
         for (int s = 0; s < S; ++s)
             if (slot_req[s] >= 0 && hs[s].status == fmdp::kRunning) list.push_back(s);
+        if (list.empty() && next_commit == next_req) {
+            // idle until the next arrival
+            const double wait = arrival_s[next_req] - now_s();
+            if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.001)));
+            continue;
+        }
         if (!list.empty()) {
             HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
@@ -448,12 +462,14 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
         HIP_TRY(hipMemcpyAsync(&done, ctx->dNdone, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipMemcpyAsync(hs.data(), ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
+        const double t_done = now_s();
         for (int q = 0; q < done; ++q) {
             const int s = order[q];
             const int r = slot_req[s];
             int rc = copy_plan_out(ctx, s, hs[s], &plans[r]);
             if (rc) return rc;
             committed[r] = hs[s].committed;
+            if (done_s) done_s[r] = t_done;
             if (hs[s].committed) {
                 for (int k = 0; k < hs[s].n_points; ++k) ctx->hRowN[hs[s].t0 + k] += 1;
                 ctx->n_plans += 1;
@@ -466,6 +482,29 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
         if (done < (int)order.size()) ctx->st_resumes += 1;   // order[done] resumes planning
         HIP_TRY(hipStreamSynchronize(ctx->stream));
     }
+    return 0;
+}
+
+int fastmdp_table_snapshot(fastmdp_ctx *ctx) {
+    if (!ctx) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->snapRowN = ctx->hRowN;
+    ctx->snap_plans = ctx->n_plans;
+    return 0;
+}
+
+int fastmdp_table_rewind(fastmdp_ctx *ctx) {
+    if (!ctx) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->snapRowN.empty()) {
+        ctx->snapRowN.assign(ctx->tb.rows, 0);
+        ctx->snap_plans = 0;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->tb.rowN, ctx->snapRowN.data(), ctx->snapRowN.size() * sizeof(int),
+                           hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->hRowN = ctx->snapRowN;
+    ctx->n_plans = ctx->snap_plans;
     return 0;
 }
 

@@ -14,6 +14,8 @@ constexpr int kTile = 2048;         // plans staged in LDS per tile (32 KiB)
 constexpr int kMaxActions = 1024;
 constexpr int kMaxHeads = kPlanThreads;
 constexpr int kRunning = -1;        // slot status while a request is being planned
+constexpr double kBand = 1e-3;      // metres: FP32 nearest distances this close to the well
+                                    // radius are recomputed exactly in FP64
 
 // Problem constants as the kernels use them (passed by value).
 struct DevCfg {
@@ -74,6 +76,13 @@ struct EvalOut {
     int *best;
 };
 
+// Squared distance, in FP64, between an FP64 point and an FP32 table entry:
+// the one separation arithmetic of the planner's exact checks and of commit.
+__device__ __forceinline__ double entry_d2(double x, double y, double z, float px, float py, float pz) {
+    const double dx = (double)px - x, dy = (double)py - y, dz = (double)pz - z;
+    return dx * dx + dy * dy + dz * dz;
+}
+
 hipError_t launch_planner(int nblk, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s, const int *list,
                           const Traj &tr, int budget, int validate, const EvalOut &ev);
 bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
@@ -82,9 +91,9 @@ bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
 hipError_t launch_fill_int(int *p, int value, int n, hipStream_t st);
 hipError_t launch_scatter_points(const DevTable &t, const float *pts, const int *rows, const int *cols, int n,
                                  hipStream_t st);
-hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const float *pts, int t0, int n, int *flag,
+hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double *pts, int t0, int n, int *flag,
                                hipStream_t st);
-hipError_t launch_commit_append(const DevTable &t, const float *pts, int t0, int n, const int *flag,
+hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, const int *flag,
                                 hipStream_t st);
 hipError_t launch_fcfs_sequencer(const DevCfg &c, const DevTable &t, Slot *slots, const int *order, int n_order,
                                  const Traj &tr, int *n_done, hipStream_t st);

@@ -55,10 +55,19 @@ struct Scored {
     double clr;         // terrain clearance (inf without terrain)
 };
 
-// Score action a from state s given the per-heading cosines and the nearest
-// plan's squared-distance offset m (min over plans of |q|^2 - 2 Delta.q).
+__device__ __forceinline__ void action_offset(const DevCfg &c, int a, double cs, double sn, double o[3]) {
+    const int v = a % c.n_speed;
+    const int cl = (a / c.n_speed) % c.n_climb;
+    const double step = c.speed[v] * c.dt;
+    o[0] = step * cs;
+    o[1] = step * sn;
+    o[2] = c.climb[cl] * c.dt;
+}
+
+// Score action a from state s given its heading's cosines and the squared
+// distance d2 from the successor to the nearest plan.
 __device__ Scored score_action(const DevCfg &c, const DevTable &tb, int a, const double s[3],
-                               const double g[3], double cs, double sn, float m) {
+                               const double g[3], double cs, double sn, double d2) {
     Scored r;
     const int v = a % c.n_speed;
     const int cl = (a / c.n_speed) % c.n_climb;
@@ -69,8 +78,6 @@ __device__ Scored score_action(const DevCfg &c, const DevTable &tb, int a, const
     r.z = s[2] + dz;
     const double ex = g[0] - r.x, ey = g[1] - r.y, ez = g[2] - r.z;
     r.G = fabs(c.r_goal) * pow(c.gamma, sqrt(ex * ex + ey * ey + ez * ez) / c.ell);
-    // squared distance to the nearest plan: m + |Delta|^2
-    const double d2 = (double)m + step * step + dz * dz;
     r.I = 0.0;
     if (d2 < c.R_intr * c.R_intr)
         r.I = fabs(c.r_intr) * pow(c.gamma_intr, sqrt(fmax(d2, 0.0)) / c.ell);
@@ -107,7 +114,8 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
     constexpr int NW = kPlanThreads / 64;
     __shared__ float4 tile[kTile];              // staged plans; reused for the slice reduction
     __shared__ double sV[kMaxActions];
-    __shared__ float sM[kMaxActions];
+    __shared__ double sD2[kMaxActions];         // squared nearest-plan distance per action
+    __shared__ unsigned sBand[kMaxActions / 32];
     __shared__ double sCos[kMaxHeads], sSin[kMaxHeads];
     __shared__ double st_s[3];
     __shared__ int st_n, st_status, st_flag;
@@ -150,12 +158,8 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
         const int n_row = t0 < tb.rows ? tb.rowN[t0] : 0;
         const size_t rb = (size_t)t0 * tb.cap;
         int hit = 0;
-        for (int j = tid; j < n_row; j += kPlanThreads) {
-            const double dx = (double)tb.X[rb + j] - o[0];
-            const double dy = (double)tb.Y[rb + j] - o[1];
-            const double dz = (double)tb.Z[rb + j] - o[2];
-            if (sqrt(dx * dx + dy * dy + dz * dz) < cfg.R_sep) hit = 1;
-        }
+        for (int j = tid; j < n_row; j += kPlanThreads)
+            if (entry_d2(o[0], o[1], o[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < cfg.R_sep * cfg.R_sep) hit = 1;
         if (hit) st_flag = 1;        // benign race: every writer stores 1
         __syncthreads();
         if (tid == 0) {
@@ -278,22 +282,59 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
         }
         __syncthreads();
 
-        // 4. per-action value
+        // 4. per-action value.  The nearest-plan squared distance is
+        //    m + |Delta|^2 with m from the FP32 sweep; actions whose distance
+        //    lands within kBand of the well radius are flagged for an exact
+        //    FP64 recomputation so that well membership is decided in FP64.
+        for (int w = tid; w < kMaxActions / 32; w += kPlanThreads) sBand[w] = 0u;
+        __syncthreads();
         for (int a = tid; a < A; a += kPlanThreads) {
             float m = INFINITY;
             for (int sl = 0; sl < n_slices; ++sl) m = fminf(m, red[sl * A + a]);
             const int h = a / (NC * NV);
-            const Scored r = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], m);
+            double o[3];
+            action_offset(cfg, a, sCos[h], sSin[h], o);
+            const double d2 = (double)m + (o[0] * o[0] + o[1] * o[1]) + o[2] * o[2];
+            const Scored r = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], d2);
             sV[a] = r.V;
-            sM[a] = m;
-            if (eval) {
+            sD2[a] = d2;
+            if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) atomicOr(&sBand[a >> 5], 1u << (a & 31));
+        }
+        __syncthreads();
+        for (int w = 0; w < (A + 31) / 32; ++w) {             // uniform loop; almost always empty
+            unsigned bits = sBand[w];
+            while (bits) {
+                const int a = w * 32 + __builtin_ctz(bits);
+                bits &= bits - 1;
+                const int h = a / (NC * NV);
+                double o[3];
+                action_offset(cfg, a, sCos[h], sSin[h], o);
+                const double px = s[0] + o[0], py = s[1] + o[1], pz = s[2] + o[2];
+                double dmin = INFINITY;
+                for (int j = tid; j < n_row; j += kPlanThreads)
+                    dmin = fmin(dmin, entry_d2(px, py, pz, tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]));
+                dmin = -wave_max(-dmin);
+                if (lane == 0) red_d[wave] = dmin;
+                __syncthreads();
+                if (tid == 0) {
+                    double d2 = red_d[0];
+                    for (int q = 1; q < NW; ++q) d2 = fmin(d2, red_d[q]);
+                    sD2[a] = d2;
+                    sV[a] = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], d2).V;
+                }
+                __syncthreads();
+            }
+        }
+        if (eval) {
+            for (int a = tid; a < A; a += kPlanThreads) {
+                const int h = a / (NC * NV);
+                const Scored r = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]);
                 if (ev.V) ev.V[a] = r.V;
                 if (ev.G) ev.G[a] = r.G;
                 if (ev.I) ev.I[a] = r.I;
                 if (ev.T) ev.T[a] = r.T;
             }
         }
-        __syncthreads();
 
         // 5. argmax: largest value, then the lowest index within the tie band
         double lv = -INFINITY;
@@ -330,7 +371,7 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
                 st_status = FASTMDP_NO_VALID_ACTION;
             } else {
                 const int h = best / (NC * NV);
-                const Scored r = score_action(cfg, tb, best, s, g, sCos[h], sSin[h], sM[best]);
+                const Scored r = score_action(cfg, tb, best, s, g, sCos[h], sSin[h], sD2[best]);
                 const size_t p = pt_base + n;
                 tr.xyz[p * 3 + 0] = r.x;
                 tr.xyz[p * 3 + 1] = r.y;
@@ -350,26 +391,21 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
     __syncthreads();   // st_status written by thread 0 on the way out of the loop
 
     // Commit validation of a finished OK trajectory against every table
-    // entry it saw: each point rounded to FP32 (the table's storage format)
-    // must be at least R_sep from every entry of its row that existed when
-    // the row was scored, and clear of the terrain.  Entries appended later
-    // are the sequencer's interaction check.
+    // entry it saw: each point as planned (FP64) must be at least R_sep from
+    // every entry of its row that existed when the row was scored, and clear
+    // of the terrain.  Entries appended later are the sequencer's
+    // interaction check.
     if (!eval && validate && st_status == FASTMDP_OK) {
         const int n = st_n;
         const double r2 = cfg.R_sep * cfg.R_sep;
         int bad = 0;
         for (int k = 0; k < n; ++k) {
             const double *x = tr.xyz + (pt_base + k) * 3;
-            const double px = (float)x[0], py = (float)x[1], pz = (float)x[2];
             const int lim = tr.seen[pt_base + k];
             const size_t rb = (size_t)(t0 + k) * tb.cap;
-            for (int j = tid; j < lim; j += kPlanThreads) {
-                const double dx = (double)tb.X[rb + j] - px;
-                const double dy = (double)tb.Y[rb + j] - py;
-                const double dz = (double)tb.Z[rb + j] - pz;
-                if (dx * dx + dy * dy + dz * dz < r2) bad = 1;
-            }
-            if (tb.terr && (k % kPlanThreads) == tid && pz - terrain_height(tb, px, py) < 0.0) bad = 1;
+            for (int j = tid; j < lim; j += kPlanThreads)
+                if (entry_d2(x[0], x[1], x[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2) bad = 1;
+            if (tb.terr && (k % kPlanThreads) == tid && x[2] - terrain_height(tb, x[0], x[1]) < 0.0) bad = 1;
         }
         if (tid == 0) st_flag = 0;
         __syncthreads();

@@ -39,43 +39,40 @@ __global__ void scatter_points_kernel(DevTable tb, const float *pts, const int *
     tb.Z[idx] = pts[3 * i + 2];
 }
 
-// Separation of point k of a trajectory (FP32 storage values, compared in
-// FP64) against every entry of its row; terrain clearance; capacity.
+// Commit validation of one trajectory point as planned (FP64) against every
+// entry of its row as stored (FP32), in FP64; terrain clearance; capacity.
 // flag bit 0: conflict, bit 1: capacity.
-__device__ int check_point(const DevCfg &c, const DevTable &tb, const float p[3], int row, int tid, int nthr) {
+__device__ int check_point(const DevCfg &c, const DevTable &tb, const double p[3], int row, int tid, int nthr) {
     if (row >= tb.rows) return 2;
     const int n_row = tb.rowN[row];
     int f = n_row >= tb.cap ? 2 : 0;
-    const double x = p[0], y = p[1], z = p[2];
+    const double r2 = c.R_sep * c.R_sep;
     const size_t rb = (size_t)row * tb.cap;
-    for (int j = tid; j < n_row; j += nthr) {
-        const double dx = (double)tb.X[rb + j] - x;
-        const double dy = (double)tb.Y[rb + j] - y;
-        const double dz = (double)tb.Z[rb + j] - z;
-        if (sqrt(dx * dx + dy * dy + dz * dz) < c.R_sep) f |= 1;
-    }
-    if (tid == 0 && tb.terr && z - table_terrain_height(tb, x, y) < 0.0) f |= 1;
+    for (int j = tid; j < n_row; j += nthr)
+        if (entry_d2(p[0], p[1], p[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2) f |= 1;
+    if (tid == 0 && tb.terr && p[2] - table_terrain_height(tb, p[0], p[1]) < 0.0) f |= 1;
     return f;
 }
 
-__global__ void commit_check_kernel(DevCfg c, DevTable tb, const float *pts, int t0, int n, int *flag) {
+__global__ void commit_check_kernel(DevCfg c, DevTable tb, const double *pts, int t0, int n, int *flag) {
     const int k = blockIdx.x;
     if (k >= n) return;
-    const float p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
+    const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     const int f = check_point(c, tb, p, t0 + k, threadIdx.x, blockDim.x);
     if (f) atomicOr(flag, f);
 }
 
-__global__ void commit_append_kernel(DevTable tb, const float *pts, int t0, int n, const int *flag) {
+// Append the trajectory rounded to FP32 (the table's storage format).
+__global__ void commit_append_kernel(DevTable tb, const double *pts, int t0, int n, const int *flag) {
     if (*flag) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int row = t0 + k;
     const int col = tb.rowN[row];
     const size_t idx = (size_t)row * tb.cap + col;
-    tb.X[idx] = pts[3 * k + 0];
-    tb.Y[idx] = pts[3 * k + 1];
-    tb.Z[idx] = pts[3 * k + 2];
+    tb.X[idx] = (float)pts[3 * k + 0];
+    tb.Y[idx] = (float)pts[3 * k + 1];
+    tb.Z[idx] = (float)pts[3 * k + 2];
     tb.rowN[row] = col + 1;
 }
 
@@ -194,14 +191,14 @@ hipError_t launch_scatter_points(const DevTable &t, const float *pts, const int 
     return hipGetLastError();
 }
 
-hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const float *pts, int t0, int n, int *flag,
+hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double *pts, int t0, int n, int *flag,
                                hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(commit_check_kernel, dim3(n), dim3(256), 0, st, c, t, pts, t0, n, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_commit_append(const DevTable &t, const float *pts, int t0, int n, const int *flag,
+hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, const int *flag,
                                 hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(commit_append_kernel, dim3((n + 255) / 256), dim3(256), 0, st, t, pts, t0, n, flag);

@@ -42,7 +42,7 @@ class _Config(C.Structure):
         ("n_head", C.c_int32), ("n_climb", C.c_int32), ("n_speed", C.c_int32),
         ("climb", C.c_double * MAX_ACT_DIM), ("speed", C.c_double * MAX_ACT_DIM),
         ("max_steps", C.c_int32), ("plan_capacity", C.c_int32), ("max_rows", C.c_int32),
-        ("max_slots", C.c_int32),
+        ("max_slots", C.c_int32), ("steps_per_launch", C.c_int32),
         ("tie_rel", C.c_double),
     ]
 
@@ -76,7 +76,9 @@ def _load_lib():
     lib.fastmdp_plan_request.argtypes = [P, C.POINTER(_Request), C.POINTER(_Plan)]
     lib.fastmdp_commit_plan.argtypes = [P, C.POINTER(_Plan)]
     lib.fastmdp_num_plans.argtypes = [P]
-    lib.fastmdp_plan_fcfs.argtypes = [P, I32, C.POINTER(_Request), C.POINTER(_Plan), ip]
+    lib.fastmdp_plan_fcfs.argtypes = [P, I32, C.POINTER(_Request), dp, C.POINTER(_Plan), ip, dp]
+    lib.fastmdp_table_snapshot.argtypes = [P]
+    lib.fastmdp_table_rewind.argtypes = [P]
     lib.fastmdp_last_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64),
                                        C.POINTER(D)]
     lib.fastmdp_save_table.argtypes = [P, C.c_char_p]
@@ -92,6 +94,7 @@ EXPORTS = [
     "fastmdp_create", "fastmdp_destroy", "fastmdp_set_stream", "fastmdp_load_plans", "fastmdp_set_terrain",
     "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_commit_plan", "fastmdp_num_plans", "fastmdp_plan_fcfs",
     "fastmdp_last_stats", "fastmdp_save_table", "fastmdp_load_table", "fastmdp_strerror",
+    "fastmdp_table_snapshot", "fastmdp_table_rewind",
 ]
 
 
@@ -117,7 +120,7 @@ def _fptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
-def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL) -> _Config:
+def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_launch: int = 0) -> _Config:
     c = _Config()
     for k in range(3):
         c.box_min[k] = float(cfg.box_min[k])
@@ -136,6 +139,7 @@ def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL) -> _Config:
     c.plan_capacity = int(cfg.plan_capacity)
     c.max_rows = int(cfg.max_rows)
     c.max_slots = int(max_slots)
+    c.steps_per_launch = int(steps_per_launch)
     c.tie_rel = float(tie_rel)
     return c
 
@@ -183,9 +187,9 @@ def _request(origin, goal, t0: int, ident: int = 0) -> _Request:
 class Context:
     """One planner context on the current HIP device."""
 
-    def __init__(self, cfg, max_slots: int = 1, tie_rel: float = TIE_REL):
+    def __init__(self, cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_launch: int = 0):
         self.cfg = cfg
-        self._c = make_config(cfg, max_slots, tie_rel)
+        self._c = make_config(cfg, max_slots, tie_rel, steps_per_launch)
         self.A = int(cfg.n_head) * len(cfg.climb) * len(cfg.speed)
         self.capacity = int(cfg.max_steps) + 1
         h = C.c_void_p()
@@ -259,10 +263,13 @@ class Context:
         p.c.status, p.c.t0, p.c.n_points = OK, int(t0), xyz.shape[0]
         return self.commit_plan(p)
 
-    def plan_fcfs(self, requests, limit: Optional[int] = None):
+    def plan_fcfs(self, requests, limit: Optional[int] = None, arrival_s=None):
         """Plan requests first-come-first-served with concurrent slots.
 
-        Returns (plans, committed) with committed a bool array.
+        With ``arrival_s`` (non-decreasing seconds), request i is admitted no
+        earlier than arrival_s[i] after the call starts.  Returns (plans,
+        committed, done_s): committed a bool array, done_s the acceptance time
+        of each request in seconds since the call started.
         """
         m = requests.n if limit is None else min(limit, requests.n)
         arr = (_Request * max(m, 1))()
@@ -273,10 +280,21 @@ class Context:
         for k in range(m):
             parr[k] = plans[k].c
         committed = np.zeros(max(m, 1), dtype=np.int32)
-        _check("fastmdp_plan_fcfs", _lib.fastmdp_plan_fcfs(self._h, m, arr, parr, _iptr(committed)))
+        done = np.zeros(max(m, 1))
+        arr_s = None
+        if arrival_s is not None:
+            arr_s = np.ascontiguousarray(np.asarray(arrival_s, dtype=np.float64)[:m])
+        _check("fastmdp_plan_fcfs", _lib.fastmdp_plan_fcfs(self._h, m, arr, _dptr(arr_s) if arr_s is not None else None,
+                                                           parr, _iptr(committed), _dptr(done)))
         for k in range(m):
             plans[k].c = parr[k]
-        return plans, committed[:m].astype(bool)
+        return plans, committed[:m].astype(bool), done[:m]
+
+    def snapshot(self) -> None:
+        _check("fastmdp_table_snapshot", _lib.fastmdp_table_snapshot(self._h))
+
+    def rewind(self) -> None:
+        _check("fastmdp_table_rewind", _lib.fastmdp_table_rewind(self._h))
 
     def stats(self) -> dict:
         v = [C.c_int64() for _ in range(4)]
@@ -291,9 +309,9 @@ class Context:
         _check("fastmdp_load_table", _lib.fastmdp_load_table(self._h, path.encode()))
 
 
-def context_for(scenario, max_slots: int = 1) -> Context:
+def context_for(scenario, max_slots: int = 1, steps_per_launch: int = 0) -> Context:
     """Context with the scenario's known plans and terrain loaded."""
-    ctx = Context(scenario.cfg, max_slots=max_slots)
+    ctx = Context(scenario.cfg, max_slots=max_slots, steps_per_launch=steps_per_launch)
     ctx.load_plans(scenario.plans)
     if scenario.terrain is not None:
         ctx.set_terrain(scenario.terrain)

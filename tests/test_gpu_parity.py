@@ -274,7 +274,7 @@ def test_fcfs_batch_equals_sequential(fm):
             c = ctx.commit_plan(p) if p.status == 0 else False
             seq.append((p, c))
     with fm.context_for(sc, max_slots=16) as ctx:
-        plans, committed = ctx.plan_fcfs(sc.requests)
+        plans, committed, _ = ctx.plan_fcfs(sc.requests)
         st = ctx.stats()
     _log(f"[fcfs batch] stats {st}")
     for q, ((p, c), b, cb) in enumerate(zip(seq, plans, committed)):
