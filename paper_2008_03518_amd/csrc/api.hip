@@ -77,7 +77,7 @@ void free_all(fastmdp_ctx *c) {
     hipFree(c->tb.X); hipFree(c->tb.Y); hipFree(c->tb.Z); hipFree(c->tb.rowN);
     hipFree(c->dTerr);
     hipFree(c->dSlots); hipFree(c->dList); hipFree(c->dOrder); hipFree(c->dNdone);
-    hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen);
+    hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen); hipFree(c->tr.top);
     hipFree(c->dEv); hipFree(c->dBest); hipFree(c->dPts); hipFree(c->dFlag);
     if (c->e0) hipEventDestroy(c->e0);
     if (c->e1) hipEventDestroy(c->e1);
@@ -103,9 +103,8 @@ int check_cfg(const fastmdp_config *c) {
 void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     std::memset(&d, 0, sizeof(d));
     for (int k = 0; k < 3; ++k) { d.box_lo[k] = c.box_min[k]; d.box_hi[k] = c.box_max[k]; }
-    double vmax = 0.0, cmax = 0.0;
+    double vmax = 0.0;
     for (int v = 0; v < c.n_speed; ++v) vmax = std::max(vmax, c.speed[v]);
-    for (int k = 0; k < c.n_climb; ++k) cmax = std::max(cmax, std::fabs(c.climb[k]));
     d.dt = c.dt;
     d.ell = vmax * c.dt;
     d.gamma = c.gamma; d.r_goal = c.r_goal;
@@ -120,8 +119,7 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     }
     d.zeta_scale = (float)(-2.0 * c.dt);
     d.tie_rel = c.tie_rel;
-    const double max_step = std::sqrt(vmax * vmax + cmax * cmax) * c.dt;
-    d.reach = std::max(c.R_intr, c.R_sep) + max_step + 1.0;
+    d.reach = std::max(c.R_intr, c.R_sep) + 1.0;
     d.n_head = c.n_head; d.n_climb = c.n_climb; d.n_speed = c.n_speed;
     d.n_actions = c.n_head * c.n_climb * c.n_speed;
     const int mid = c.n_climb / 2;
@@ -214,6 +212,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->tr.act, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.val, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.seen, ssz);
+    rc = rc ? rc : dev_alloc(&c->tr.top, ssz);
     rc = rc ? rc : dev_alloc(&c->dEv, (size_t)4 * c->A);
     rc = rc ? rc : dev_alloc(&c->dBest, (size_t)1);
     rc = rc ? rc : dev_alloc(&c->dPts, (size_t)c->stride * 3);
@@ -413,6 +412,7 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
     std::vector<int> req_slot(n, -1);
     int next_req = 0, next_commit = 0;
     std::vector<int> list, order;
+    std::vector<char> checked_since_commit(S, 0);   // slot already checked against the current table
     while (next_commit < n) {
         // admit arrived requests into free slots, in request order
         bool dirty = false;
@@ -446,23 +446,31 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             HIP_TRY(hipMemcpyAsync(hs.data(), ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipStreamSynchronize(ctx->stream));
         }
-        // the finished prefix in request order goes to the sequencer
+        // every finished request goes to the sequencer in request order; the
+        // leading consecutive ones (from next_commit) may be accepted
         order.clear();
+        int n_prefix = 0;
+        bool gap = false;
         for (int r = next_commit; r < next_req; ++r) {
             const int s = req_slot[r];
-            if (hs[s].status == fmdp::kRunning) break;
+            if (hs[s].status == fmdp::kRunning) { gap = true; continue; }
             order.push_back(s);
+            if (!gap) ++n_prefix;
         }
-        if (order.empty()) continue;
+        if (order.empty() || (n_prefix == 0 && !checked_since_commit.empty() &&
+                              std::all_of(order.begin(), order.end(), [&](int s) { return checked_since_commit[s]; })))
+            continue;
         HIP_TRY(hipMemcpyAsync(ctx->dOrder, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice,
                                ctx->stream));
-        HIP_TRY(fmdp::launch_fcfs_sequencer(ctx->dc, ctx->tb, ctx->dSlots, ctx->dOrder, (int)order.size(), ctx->tr,
-                                            ctx->dNdone, ctx->stream));
+        HIP_TRY(fmdp::launch_fcfs_sequencer(ctx->dc, ctx->tb, ctx->dSlots, ctx->dOrder, (int)order.size(), n_prefix,
+                                            ctx->tr, ctx->dNdone, ctx->stream));
         int done = 0;
         HIP_TRY(hipMemcpyAsync(&done, ctx->dNdone, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipMemcpyAsync(hs.data(), ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
         const double t_done = now_s();
+        for (int s : order) checked_since_commit[s] = 1;
+        if (done > 0) std::fill(checked_since_commit.begin(), checked_since_commit.end(), 0);
         for (int q = 0; q < done; ++q) {
             const int s = order[q];
             const int r = slot_req[s];
@@ -479,7 +487,8 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             slot_req[s] = -1;
             ++next_commit;
         }
-        if (done < (int)order.size()) ctx->st_resumes += 1;   // order[done] resumes planning
+        for (size_t q = done; q < order.size(); ++q)
+            if (hs[order[q]].status == fmdp::kRunning) ctx->st_resumes += 1;
         HIP_TRY(hipStreamSynchronize(ctx->stream));
     }
     return 0;

@@ -27,8 +27,8 @@ struct DevCfg {
     float climb_f[FASTMDP_MAX_ACT_DIM];  // climb rates
     float zeta_scale;                    // -2 * dt
     double tie_rel;
-    double reach;                        // R_intr + max |Delta| + 1 m: plans farther than this
-                                         // from a state cannot change any of its successors' values
+    double reach;                        // max(R_intr, R_sep) + 1 m: a plan farther than this from
+                                         // a successor cannot change its value
     int n_head, n_climb, n_speed, n_actions;
     int zero_climb;                      // index of the zero climb rate in the middle, else -1
     int max_steps;
@@ -61,12 +61,15 @@ struct Slot {
 
 // Per-slot trajectory buffers, `stride` points per slot.  seen[k] is the
 // number of entries of the row scored to produce point k (for k = 0: the
-// departure row of the origin check).
+// departure row of the origin check).  top[k] is the action with the largest
+// value at that step when the chosen action (the lowest index inside the
+// tie band) is not itself the largest, else -1.
 struct Traj {
     double *xyz;
     int *act;
     double *val;
     int *seen;
+    int *top;
     int stride;
 };
 
@@ -96,6 +99,6 @@ hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double 
 hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, const int *flag,
                                 hipStream_t st);
 hipError_t launch_fcfs_sequencer(const DevCfg &c, const DevTable &t, Slot *slots, const int *order, int n_order,
-                                 const Traj &tr, int *n_done, hipStream_t st);
+                                 int n_prefix, const Traj &tr, int *n_done, hipStream_t st);
 
 }  // namespace fmdp

@@ -170,6 +170,7 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
             tr.act[pt_base] = -1;
             tr.val[pt_base] = 0.0;
             tr.seen[pt_base] = n_row;
+            tr.top[pt_base] = -1;
             st_n = 1;
             if (blocked) st_status = FASTMDP_REJECT_ORIGIN;
         }
@@ -356,6 +357,21 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
 #pragma unroll
         for (int w = 1; w < NW; ++w) best = red_i[w] < best ? red_i[w] : best;
         if (vmax == -INFINITY) best = -1;
+        // inside the tie band the chosen action may not be the largest one:
+        // remember the (lowest-index) largest for the acceptance check
+        int top = -1;
+        if (best >= 0 && sV[best] < vmax) {                // uniform
+            int ti = 0x7fffffff;
+            for (int a = tid; a < A; a += kPlanThreads)
+                if (sV[a] == vmax) { ti = a; break; }
+            ti = wave_min(ti);
+            __syncthreads();
+            if (lane == 0) red_i[wave] = ti;
+            __syncthreads();
+            top = red_i[0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) top = red_i[w] < top ? red_i[w] : top;
+        }
 
         pairs += (long long)A * n_row;
         steps_here += 1;
@@ -379,6 +395,7 @@ __global__ __launch_bounds__(kPlanThreads) void planner_kernel(DevCfg cfg, DevTa
                 tr.act[p] = best;
                 tr.val[p] = r.V;
                 tr.seen[p] = n_row;
+                tr.top[p] = top;
                 st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
                 st_n = n + 1;
                 if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;

@@ -79,24 +79,31 @@ __global__ void commit_append_kernel(DevTable tb, const double *pts, int t0, int
 constexpr int kSeqThreads = 1024;
 
 // Accept finished slots in the given (request) order.  For each slot:
-//   1. Interaction check: every table entry appended after the slot scored a
-//      row (entries [seen[k], rowN) of the row that produced point k) is
-//      compared with the state the row was scored from.  An entry farther
-//      than `reach` cannot change any successor's value, so if none is
-//      closer the trajectory equals the one planned against the full table.
-//      Otherwise the slot keeps its first k points and is re-planned from
-//      there (status back to running) and the sequencer stops: later
-//      requests wait for it.  For the origin (k = 0) the test is the origin
-//      check itself (R_sep) and the request restarts.
-//   2. An OK trajectory that the planning workgroup validated against the
+//   1. Interaction check (every listed slot, also behind a blocked head).  A plan appended after a row was scored can only
+//      add penalties, so every action's value at that step can only fall;
+//      the chosen action therefore stays chosen, with the same value, unless
+//      the new plan changes the chosen successor's own value (or, when the
+//      choice was made inside the tie band, the largest action's value).  A
+//      new entry (entries [seen[k], rowN) of the row that produced point k)
+//      can change a successor's value only within the well radius of it;
+//      `reach` adds 1 m to cover the planner's FP32 arithmetic.  If none is
+//      that close the trajectory equals the one planned against the full
+//      table, and the checked entries count as seen.  Otherwise the slot
+//      keeps its first k points and is re-planned from there (status back to
+//      running); later requests cannot be accepted before it.  For the origin
+//      (k = 0) the test is the origin check itself and the request restarts.
+//   2. Acceptance, in order, of the leading slots (the first n_prefix listed
+//      are consecutive requests) up to the first one that is re-planned: an
+//      OK trajectory that the planning workgroup validated against the
 //      entries it saw (Slot::valid) is appended if its rows have room.
 __global__ __launch_bounds__(kSeqThreads) void fcfs_sequencer_kernel(DevCfg c, DevTable tb, Slot *slots,
-                                                                     const int *order, int n_order, Traj tr,
-                                                                     int *n_done) {
+                                                                     const int *order, int n_order, int n_prefix,
+                                                                     Traj tr, int *n_done) {
     __shared__ int s_first, s_flag;
     const int tid = threadIdx.x;
-    int q = 0;
-    for (; q < n_order; ++q) {
+    const double r2 = c.reach * c.reach;
+    int blocked = 0, accepted = 0;                         // uniform
+    for (int q = 0; q < n_order; ++q) {
         Slot &S = slots[order[q]];
         const int n = S.n_points;
         const int t0 = S.t0;
@@ -110,32 +117,50 @@ __global__ __launch_bounds__(kSeqThreads) void fcfs_sequencer_kernel(DevCfg c, D
             const int hi = tb.rowN[row];
             const int lo = tr.seen[base + k];
             if (lo >= hi) continue;
-            // state the row was scored from: the origin for k = 0 (origin
-            // check), else point k-1
-            const double *sp = tr.xyz + (base + (k == 0 ? 0 : k - 1)) * 3;
-            const double r = k == 0 ? c.R_sep + 1.0 : c.reach;
+            const double *x = tr.xyz + (base + k) * 3;     // chosen successor (the origin for k = 0)
+            double y[3] = {x[0], x[1], x[2]};              // largest action's successor, if different
+            const int top = k > 0 ? tr.top[base + k] : -1;
+            if (top >= 0) {
+                const double *sp = tr.xyz + (base + k - 1) * 3;
+                const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
+                const double beta = (bx == 0.0 && by == 0.0) ? 0.0 : atan2(by, bx);
+                const int h = top / (c.n_climb * c.n_speed);
+                const int cl = (top / c.n_speed) % c.n_climb;
+                const int v = top % c.n_speed;
+                const double th = beta + 2.0 * M_PI * (double)h / (double)c.n_head;
+                const double step = c.speed[v] * c.dt;
+                y[0] = sp[0] + step * cos(th);
+                y[1] = sp[1] + step * sin(th);
+                y[2] = sp[2] + c.climb[cl] * c.dt;
+            }
             const size_t rb = (size_t)row * tb.cap;
+            bool hit = false;
             for (int j = lo; j < hi; ++j) {
-                const double dx = (double)tb.X[rb + j] - sp[0];
-                const double dy = (double)tb.Y[rb + j] - sp[1];
-                const double dz = (double)tb.Z[rb + j] - sp[2];
-                if (sqrt(dx * dx + dy * dy + dz * dz) < r) {
-                    atomicMin(&s_first, k);
+                const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
+                if (entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2) {
+                    hit = true;
                     break;
                 }
             }
+            if (hit) atomicMin(&s_first, k);
+            else tr.seen[base + k] = hi;                   // entries [lo, hi) are accounted for
         }
         __syncthreads();
         const int first = s_first;
         if (first != 0x7fffffff) {
+            // affected: re-plan from the first affected step right away, even
+            // behind a blocked head, so that re-plans overlap
             if (tid == 0) {
                 S.resume_at = first;
                 S.n_points = first;          // keep points 0..first-1; re-score from point first-1
                 S.status = kRunning;
                 S.committed = 0;
             }
-            break;
+            blocked = 1;
+            __syncthreads();
+            continue;
         }
+        if (blocked || q >= n_prefix) continue;            // clean, but an earlier request is not final
 
         if (S.status == FASTMDP_OK && S.valid) {
             // entries [0, seen[k]) were validated by the planning workgroup and
@@ -171,9 +196,10 @@ __global__ __launch_bounds__(kSeqThreads) void fcfs_sequencer_kernel(DevCfg c, D
             S.committed = 0;
             S.resume_at = -1;
         }
+        accepted = q + 1;
         __syncthreads();
     }
-    if (tid == 0) *n_done = q;
+    if (tid == 0) *n_done = accepted;
 }
 
 }  // namespace
@@ -206,9 +232,9 @@ hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, in
 }
 
 hipError_t launch_fcfs_sequencer(const DevCfg &c, const DevTable &t, Slot *slots, const int *order, int n_order,
-                                 const Traj &tr, int *n_done, hipStream_t st) {
-    hipLaunchKernelGGL(fcfs_sequencer_kernel, dim3(1), dim3(kSeqThreads), 0, st, c, t, slots, order, n_order, tr,
-                       n_done);
+                                 int n_prefix, const Traj &tr, int *n_done, hipStream_t st) {
+    hipLaunchKernelGGL(fcfs_sequencer_kernel, dim3(1), dim3(kSeqThreads), 0, st, c, t, slots, order, n_order,
+                       n_prefix, tr, n_done);
     return hipGetLastError();
 }
 
