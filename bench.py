@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--slots", type=int, default=512)
     ap.add_argument("--steps-per-launch", type=int, default=256)
+    ap.add_argument("--planner-threads", type=int, default=0, help="256, 1024 or 0 (auto)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals [req/s]; 0 disables")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work; 0 disables")
@@ -79,7 +80,8 @@ def main():
                       sc.requests.goal[:args.requests], sc.requests.t0[:args.requests])
     log(f"workload: {sc.plans.n} plans, {cfg.n_actions} actions, {reqs.n} requests, slots {args.slots}")
 
-    ctx = fm.context_for(sc, max_slots=args.slots, steps_per_launch=args.steps_per_launch)
+    ctx = fm.context_for(sc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
+                         planner_threads=args.planner_threads)
     ctx.snapshot()
 
     def one_step():
@@ -127,6 +129,7 @@ def main():
                         f"dt 0.5 s, {reqs.n} FCFS requests, 30x30x1.5 km",
             "known_plans": sc.plans.n, "actions": cfg.n_actions, "requests_per_step": reqs.n,
             "slots": args.slots, "steps_per_launch": args.steps_per_launch,
+            "planner_threads": args.planner_threads,
         },
         "pair_evals_per_s": pairs / (kms * 1e-3),
         "planner_steps": steps,

@@ -37,6 +37,7 @@ struct fastmdp_ctx {
     int snap_plans = 0;
     float *dTerr = nullptr;
     int max_slots = 1, stride = 0;
+    int n_cu = 256;                       // compute units of the device
     Slot *dSlots = nullptr;
     int *dList = nullptr, *dOrder = nullptr, *dNdone = nullptr;
     Traj tr{};
@@ -111,6 +112,12 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.r_intr = c.r_intr; d.R_intr = c.R_intr; d.gamma_intr = c.gamma_intr;
     d.R_sep = c.R_sep;
     d.r_terr = c.r_terr; d.R_terr = c.R_terr; d.gamma_terr = c.gamma_terr;
+    d.log_gamma = std::log(c.gamma);
+    d.log_gamma_intr = std::log(c.gamma_intr);
+    d.log_gamma_terr = std::log(c.gamma_terr);
+    d.abs_r_goal = std::fabs(c.r_goal);
+    d.abs_r_intr = std::fabs(c.r_intr);
+    d.abs_r_terr = std::fabs(c.r_terr);
     for (int k = 0; k < FASTMDP_MAX_ACT_DIM; ++k) {
         d.climb[k] = c.climb[k];
         d.speed[k] = c.speed[k];
@@ -128,8 +135,11 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
 }
 
 int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int validate, const EvalOut &ev) {
+    // one request per CU (1024 threads) while that fits the chip, else several
+    int nt = c->cfg.planner_threads;
+    if (nt != 256 && nt != 1024) nt = nblk <= c->n_cu ? 1024 : 256;
     HIP_TRY(hipEventRecord(c->e0, c->stream));
-    hipError_t e = fmdp::launch_planner(nblk, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate, ev);
+    hipError_t e = fmdp::launch_planner(nblk, nt, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate, ev);
     if (e != hipSuccess) {
         std::fprintf(stderr, "libfastmdp: planner launch failed: %s\n", hipGetErrorString(e));
         return FASTMDP_E_DEVICE;
@@ -227,6 +237,12 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     }
     c->stream = c->own;
     c->tr.stride = c->stride;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->n_cu = cus;
+    }
     c->hRowN.assign(cfg->max_rows, 0);
     if (fmdp::launch_fill_int(c->tb.rowN, 0, cfg->max_rows, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {

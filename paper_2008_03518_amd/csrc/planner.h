@@ -9,10 +9,8 @@
 
 namespace fmdp {
 
-constexpr int kPlanThreads = 256;   // planning workgroup: 4 wave64
-constexpr int kTile = 2048;         // plans staged in LDS per tile (32 KiB)
 constexpr int kMaxActions = 1024;
-constexpr int kMaxHeads = kPlanThreads;
+constexpr int kMaxHeads = 128;
 constexpr int kRunning = -1;        // slot status while a request is being planned
 constexpr double kBand = 1e-3;      // metres: FP32 nearest distances this close to the well
                                     // radius are recomputed exactly in FP64
@@ -22,6 +20,8 @@ struct DevCfg {
     double box_lo[3], box_hi[3];
     double dt, ell;
     double gamma, r_goal, r_intr, R_intr, gamma_intr, R_sep, r_terr, R_terr, gamma_terr;
+    double log_gamma, log_gamma_intr, log_gamma_terr;   // discounts as exp(log_gamma * distance/ell)
+    double abs_r_goal, abs_r_intr, abs_r_terr;
     double climb[FASTMDP_MAX_ACT_DIM], speed[FASTMDP_MAX_ACT_DIM];
     float kv[FASTMDP_MAX_ACT_DIM];       // -2 * speed * dt
     float climb_f[FASTMDP_MAX_ACT_DIM];  // climb rates
@@ -86,8 +86,9 @@ __device__ __forceinline__ double entry_d2(double x, double y, double z, float p
     return dx * dx + dy * dy + dz * dz;
 }
 
-hipError_t launch_planner(int nblk, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s, const int *list,
-                          const Traj &tr, int budget, int validate, const EvalOut &ev);
+// nt: workgroup size, 256 (several requests per CU) or 1024 (one request per CU)
+hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
+                          const int *list, const Traj &tr, int budget, int validate, const EvalOut &ev);
 bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
 
 // table.hip

@@ -77,94 +77,112 @@ __global__ void commit_append_kernel(DevTable tb, const double *pts, int t0, int
 }
 
 constexpr int kSeqThreads = 1024;
+constexpr int kCheckThreads = 256;
 
-// Accept finished slots in the given (request) order.  For each slot:
-//   1. Interaction check (every listed slot, also behind a blocked head).  A plan appended after a row was scored can only
-//      add penalties, so every action's value at that step can only fall;
-//      the chosen action therefore stays chosen, with the same value, unless
-//      the new plan changes the chosen successor's own value (or, when the
-//      choice was made inside the tie band, the largest action's value).  A
-//      new entry (entries [seen[k], rowN) of the row that produced point k)
-//      can change a successor's value only within the well radius of it;
-//      `reach` adds 1 m to cover the planner's FP32 arithmetic.  If none is
-//      that close the trajectory equals the one planned against the full
-//      table, and the checked entries count as seen.  Otherwise the slot
-//      keeps its first k points and is re-planned from there (status back to
-//      running); later requests cannot be accepted before it.  For the origin
-//      (k = 0) the test is the origin check itself and the request restarts.
-//   2. Acceptance, in order, of the leading slots (the first n_prefix listed
-//      are consecutive requests) up to the first one that is re-planned: an
-//      OK trajectory that the planning workgroup validated against the
-//      entries it saw (Slot::valid) is appended if its rows have room.
-__global__ __launch_bounds__(kSeqThreads) void fcfs_sequencer_kernel(DevCfg c, DevTable tb, Slot *slots,
-                                                                     const int *order, int n_order, int n_prefix,
-                                                                     Traj tr, int *n_done) {
+// Interaction check of one finished trajectory against the table entries
+// appended after it scored their rows.  A plan committed after a row was
+// scored can only add penalties, so every action's value at that step can
+// only fall: the chosen action stays chosen, with the same value, unless the
+// new plan changes the chosen successor's own value (or, when the choice was
+// made inside the tie band, the largest action's value).  A new entry
+// (entries [seen[k], rowN) of the row that produced point k) can change a
+// successor's value only within the well radius of it; `reach` adds 1 m to
+// cover the planner's FP32 arithmetic.  For the origin (k = 0) the test is
+// the origin check.  Clean steps record the checked entries as seen.
+// Returns (through *first) the first affected point, untouched if none.
+__device__ void check_interactions(const DevCfg &c, const DevTable &tb, const Slot &S, const Traj &tr,
+                                   size_t base, int tid, int nthr, int *first) {
+    const double r2 = c.reach * c.reach;
+    const int n = S.n_points, t0 = S.t0;
+    for (int k = tid; k < n; k += nthr) {
+        const int row = t0 + k;
+        if (row >= tb.rows) continue;
+        const int hi = tb.rowN[row];
+        const int lo = tr.seen[base + k];
+        if (lo >= hi) continue;
+        const double *x = tr.xyz + (base + k) * 3;     // chosen successor (the origin for k = 0)
+        double y[3] = {x[0], x[1], x[2]};              // largest action's successor, if different
+        const int top = k > 0 ? tr.top[base + k] : -1;
+        if (top >= 0) {
+            const double *sp = tr.xyz + (base + k - 1) * 3;
+            const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
+            const double r = sqrt(bx * bx + by * by);
+            const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
+            const int h = top / (c.n_climb * c.n_speed);
+            const int cl = (top / c.n_speed) % c.n_climb;
+            const int v = top % c.n_speed;
+            const double th = 2.0 * M_PI * (double)h / (double)c.n_head;
+            const double c0 = cos(th), s0 = sin(th);
+            const double step = c.speed[v] * c.dt;
+            y[0] = sp[0] + step * (cb * c0 - sb * s0);
+            y[1] = sp[1] + step * (sb * c0 + cb * s0);
+            y[2] = sp[2] + c.climb[cl] * c.dt;
+        }
+        const size_t rb = (size_t)row * tb.cap;
+        bool hit = false;
+        for (int j = lo; j < hi; ++j) {
+            const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
+            if (entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2) {
+                hit = true;
+                break;
+            }
+        }
+        if (hit) atomicMin(first, k);
+        else tr.seen[base + k] = hi;
+    }
+}
+
+__device__ void resume_from(Slot &S, int first) {
+    S.resume_at = first;
+    S.n_points = first;          // keep points 0..first-1; re-score from point first-1
+    S.status = kRunning;
+    S.committed = 0;
+}
+
+// Every finished, not yet accepted slot against everything committed so far
+// (one workgroup per slot, in parallel).  An affected slot goes back to
+// planning from its first affected step at once, so that re-plans overlap.
+__global__ __launch_bounds__(kCheckThreads) void fcfs_check_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                   const int *order, Traj tr) {
+    __shared__ int s_first;
+    const int slot = order[blockIdx.x];
+    Slot &S = slots[slot];
+    if (threadIdx.x == 0) s_first = 0x7fffffff;
+    __syncthreads();
+    check_interactions(c, tb, S, tr, (size_t)slot * tr.stride, threadIdx.x, kCheckThreads, &s_first);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_first != 0x7fffffff) resume_from(S, s_first);
+}
+
+// Acceptance in request order of the leading slots (the first n_prefix
+// listed are consecutive requests; all were just checked against the table)
+// up to the first one that must be re-planned.  Each is checked against the
+// plans accepted earlier in this pass, then an OK trajectory that the
+// planning workgroup validated against the entries it saw (Slot::valid) is
+// appended if its rows have room.
+__global__ __launch_bounds__(kSeqThreads) void fcfs_accept_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                  const int *order, int n_prefix, Traj tr,
+                                                                  int *n_done) {
     __shared__ int s_first, s_flag;
     const int tid = threadIdx.x;
-    const double r2 = c.reach * c.reach;
-    int blocked = 0, accepted = 0;                         // uniform
-    for (int q = 0; q < n_order; ++q) {
+    int accepted = 0;                                      // uniform
+    for (int q = 0; q < n_prefix; ++q) {
         Slot &S = slots[order[q]];
+        if (S.status == kRunning) break;                  // re-planned by the check pass
         const int n = S.n_points;
         const int t0 = S.t0;
         const size_t base = (size_t)order[q] * tr.stride;
         if (tid == 0) { s_first = 0x7fffffff; s_flag = 0; }
         __syncthreads();
-
-        for (int k = tid; k < n; k += kSeqThreads) {
-            const int row = t0 + k;
-            if (row >= tb.rows) continue;
-            const int hi = tb.rowN[row];
-            const int lo = tr.seen[base + k];
-            if (lo >= hi) continue;
-            const double *x = tr.xyz + (base + k) * 3;     // chosen successor (the origin for k = 0)
-            double y[3] = {x[0], x[1], x[2]};              // largest action's successor, if different
-            const int top = k > 0 ? tr.top[base + k] : -1;
-            if (top >= 0) {
-                const double *sp = tr.xyz + (base + k - 1) * 3;
-                const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
-                const double beta = (bx == 0.0 && by == 0.0) ? 0.0 : atan2(by, bx);
-                const int h = top / (c.n_climb * c.n_speed);
-                const int cl = (top / c.n_speed) % c.n_climb;
-                const int v = top % c.n_speed;
-                const double th = beta + 2.0 * M_PI * (double)h / (double)c.n_head;
-                const double step = c.speed[v] * c.dt;
-                y[0] = sp[0] + step * cos(th);
-                y[1] = sp[1] + step * sin(th);
-                y[2] = sp[2] + c.climb[cl] * c.dt;
-            }
-            const size_t rb = (size_t)row * tb.cap;
-            bool hit = false;
-            for (int j = lo; j < hi; ++j) {
-                const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
-                if (entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2) {
-                    hit = true;
-                    break;
-                }
-            }
-            if (hit) atomicMin(&s_first, k);
-            else tr.seen[base + k] = hi;                   // entries [lo, hi) are accounted for
-        }
+        check_interactions(c, tb, S, tr, base, tid, kSeqThreads, &s_first);
         __syncthreads();
-        const int first = s_first;
-        if (first != 0x7fffffff) {
-            // affected: re-plan from the first affected step right away, even
-            // behind a blocked head, so that re-plans overlap
-            if (tid == 0) {
-                S.resume_at = first;
-                S.n_points = first;          // keep points 0..first-1; re-score from point first-1
-                S.status = kRunning;
-                S.committed = 0;
-            }
-            blocked = 1;
-            __syncthreads();
-            continue;
+        if (s_first != 0x7fffffff) {
+            if (tid == 0) resume_from(S, s_first);
+            break;
         }
-        if (blocked || q >= n_prefix) continue;            // clean, but an earlier request is not final
-
         if (S.status == FASTMDP_OK && S.valid) {
             // entries [0, seen[k]) were validated by the planning workgroup and
-            // the interaction check above clears the rest; only capacity is left
+            // the interaction checks cleared the rest; only capacity is left
             if (tid == 0) s_flag = (t0 + n > tb.rows) ? 2 : 0;
             __syncthreads();
             for (int k = tid; k < n && s_flag == 0; k += kSeqThreads)
@@ -233,8 +251,10 @@ hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, in
 
 hipError_t launch_fcfs_sequencer(const DevCfg &c, const DevTable &t, Slot *slots, const int *order, int n_order,
                                  int n_prefix, const Traj &tr, int *n_done, hipStream_t st) {
-    hipLaunchKernelGGL(fcfs_sequencer_kernel, dim3(1), dim3(kSeqThreads), 0, st, c, t, slots, order, n_order,
-                       n_prefix, tr, n_done);
+    if (n_order > 0)
+        hipLaunchKernelGGL(fcfs_check_kernel, dim3(n_order), dim3(kCheckThreads), 0, st, c, t, slots, order, tr);
+    hipLaunchKernelGGL(fcfs_accept_kernel, dim3(1), dim3(kSeqThreads), 0, st, c, t, slots, order, n_prefix, tr,
+                       n_done);
     return hipGetLastError();
 }
 

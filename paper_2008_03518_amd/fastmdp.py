@@ -42,7 +42,7 @@ class _Config(C.Structure):
         ("n_head", C.c_int32), ("n_climb", C.c_int32), ("n_speed", C.c_int32),
         ("climb", C.c_double * MAX_ACT_DIM), ("speed", C.c_double * MAX_ACT_DIM),
         ("max_steps", C.c_int32), ("plan_capacity", C.c_int32), ("max_rows", C.c_int32),
-        ("max_slots", C.c_int32), ("steps_per_launch", C.c_int32),
+        ("max_slots", C.c_int32), ("steps_per_launch", C.c_int32), ("planner_threads", C.c_int32),
         ("tie_rel", C.c_double),
     ]
 
@@ -120,7 +120,8 @@ def _fptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
-def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_launch: int = 0) -> _Config:
+def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_launch: int = 0,
+                planner_threads: int = 0) -> _Config:
     c = _Config()
     for k in range(3):
         c.box_min[k] = float(cfg.box_min[k])
@@ -140,6 +141,7 @@ def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_lau
     c.max_rows = int(cfg.max_rows)
     c.max_slots = int(max_slots)
     c.steps_per_launch = int(steps_per_launch)
+    c.planner_threads = int(planner_threads)
     c.tie_rel = float(tie_rel)
     return c
 
@@ -187,9 +189,10 @@ def _request(origin, goal, t0: int, ident: int = 0) -> _Request:
 class Context:
     """One planner context on the current HIP device."""
 
-    def __init__(self, cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_launch: int = 0):
+    def __init__(self, cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_launch: int = 0,
+                 planner_threads: int = 0):
         self.cfg = cfg
-        self._c = make_config(cfg, max_slots, tie_rel, steps_per_launch)
+        self._c = make_config(cfg, max_slots, tie_rel, steps_per_launch, planner_threads)
         self.A = int(cfg.n_head) * len(cfg.climb) * len(cfg.speed)
         self.capacity = int(cfg.max_steps) + 1
         h = C.c_void_p()
@@ -309,9 +312,10 @@ class Context:
         _check("fastmdp_load_table", _lib.fastmdp_load_table(self._h, path.encode()))
 
 
-def context_for(scenario, max_slots: int = 1, steps_per_launch: int = 0) -> Context:
+def context_for(scenario, max_slots: int = 1, steps_per_launch: int = 0, planner_threads: int = 0) -> Context:
     """Context with the scenario's known plans and terrain loaded."""
-    ctx = Context(scenario.cfg, max_slots=max_slots, steps_per_launch=steps_per_launch)
+    ctx = Context(scenario.cfg, max_slots=max_slots, steps_per_launch=steps_per_launch,
+                  planner_threads=planner_threads)
     ctx.load_plans(scenario.plans)
     if scenario.terrain is not None:
         ctx.set_terrain(scenario.terrain)
