@@ -58,9 +58,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plans", type=int, default=3000)
     ap.add_argument("--requests", type=int, default=1000)
-    ap.add_argument("--slots", type=int, default=512)
+    ap.add_argument("--slots", type=int, default=1024)
     ap.add_argument("--steps-per-launch", type=int, default=256)
-    ap.add_argument("--planner-threads", type=int, default=0, help="256, 1024 or 0 (auto)")
+    ap.add_argument("--planner-threads", type=int, default=0, help="planning workgroup size: 0 or 1024")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals [req/s]; 0 disables")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work; 0 disables")

@@ -84,9 +84,8 @@ typedef struct {
     int32_t max_slots;               /* requests planned concurrently (>= 1)      */
     int32_t steps_per_launch;        /* FCFS engine: steps per slot between
                                         acceptance passes (0: 256)                */
-    int32_t planner_threads;         /* planning workgroup size: 256 or 1024;
-                                        0 picks 1024 while the requests in flight
-                                        fit one per compute unit                  */
+    int32_t planner_threads;         /* planning workgroup size: 0 or 1024 (one
+                                        request per compute unit)                 */
     double tie_rel;                  /* argmax: values within tie_rel*|max| of the
                                         maximum tie; the lowest index wins        */
 } fastmdp_config;

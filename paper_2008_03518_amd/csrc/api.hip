@@ -19,6 +19,7 @@
 #include "fastmdp.h"
 #include "planner.h"
 
+using fmdp::DeathLog;
 using fmdp::DevCfg;
 using fmdp::DevTable;
 using fmdp::EvalOut;
@@ -33,6 +34,7 @@ struct fastmdp_ctx {
     hipStream_t own = nullptr, stream = nullptr;
     std::vector<int> hRowN;
     int n_plans = 0;
+    int seq = 0;                          // next request sequence number (table entry owners are below it)
     std::vector<int> snapRowN;            // table snapshot (row counts)
     int snap_plans = 0;
     float *dTerr = nullptr;
@@ -45,6 +47,15 @@ struct fastmdp_ctx {
     int *dBest = nullptr;
     double *dPts = nullptr;       // stride*3 commit staging (FP64 trajectory)
     int *dFlag = nullptr;
+    // FCFS withdrawal log
+    int *dDlRow = nullptr, *dDlCol = nullptr, *dDlEp = nullptr, *dDlLen = nullptr, *dDlStart = nullptr;
+    int dl_cap = 0, dl_start_cap = 0;
+    // pinned host mirrors and the trajectory gather buffers of the FCFS engine
+    Slot *hSlots = nullptr;
+    int *dList2 = nullptr;
+    long long *dOff = nullptr;
+    void *dGather = nullptr, *hGather = nullptr;
+    size_t gather_cap = 0;                // bytes
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::mutex mu;
     // counters of the last call
@@ -76,10 +87,16 @@ int dev_alloc(T **p, size_t n) {
 
 void free_all(fastmdp_ctx *c) {
     hipFree(c->tb.X); hipFree(c->tb.Y); hipFree(c->tb.Z); hipFree(c->tb.rowN);
+    hipFree(c->tb.vis); hipFree(c->tb.own); hipFree(c->tb.dead);
+    hipFree(c->dDlRow); hipFree(c->dDlCol); hipFree(c->dDlEp); hipFree(c->dDlLen); hipFree(c->dDlStart);
     hipFree(c->dTerr);
     hipFree(c->dSlots); hipFree(c->dList); hipFree(c->dOrder); hipFree(c->dNdone);
     hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen); hipFree(c->tr.top);
+    hipFree(c->tr.ep); hipFree(c->tr.col);
     hipFree(c->dEv); hipFree(c->dBest); hipFree(c->dPts); hipFree(c->dFlag);
+    if (c->hSlots) hipHostFree(c->hSlots);
+    if (c->hGather) hipHostFree(c->hGather);
+    hipFree(c->dGather); hipFree(c->dList2); hipFree(c->dOff);
     if (c->e0) hipEventDestroy(c->e0);
     if (c->e1) hipEventDestroy(c->e1);
     if (c->own) hipStreamDestroy(c->own);
@@ -98,6 +115,7 @@ int check_cfg(const fastmdp_config *c) {
         if (!(c->speed[v] > 0.0)) return FASTMDP_E_INVAL;
     if (c->max_steps < 1 || c->plan_capacity < 1 || c->max_rows < 2) return FASTMDP_E_INVAL;
     if (!(c->tie_rel >= 0.0)) return FASTMDP_E_INVAL;
+    if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads) return FASTMDP_E_INVAL;
     return 0;
 }
 
@@ -118,6 +136,12 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.abs_r_goal = std::fabs(c.r_goal);
     d.abs_r_intr = std::fabs(c.r_intr);
     d.abs_r_terr = std::fabs(c.r_terr);
+    d.log2_gamma_f = (float)std::log2(c.gamma);
+    d.log2_gamma_intr_f = (float)std::log2(c.gamma_intr);
+    d.inv_ell_f = (float)(1.0 / d.ell);
+    d.abs_r_goal_f = (float)d.abs_r_goal;
+    d.abs_r_intr_f = (float)d.abs_r_intr;
+    d.R_intr2_f = (float)(c.R_intr * c.R_intr);
     for (int k = 0; k < FASTMDP_MAX_ACT_DIM; ++k) {
         d.climb[k] = c.climb[k];
         d.speed[k] = c.speed[k];
@@ -127,6 +151,9 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.zeta_scale = (float)(-2.0 * c.dt);
     d.tie_rel = c.tie_rel;
     d.reach = std::max(c.R_intr, c.R_sep) + 1.0;
+    double cmax = 0.0;
+    for (int k = 0; k < c.n_climb; ++k) cmax = std::max(cmax, std::fabs(c.climb[k]));
+    d.reach_state = d.reach + std::sqrt(vmax * vmax + cmax * cmax) * c.dt;
     d.n_head = c.n_head; d.n_climb = c.n_climb; d.n_speed = c.n_speed;
     d.n_actions = c.n_head * c.n_climb * c.n_speed;
     const int mid = c.n_climb / 2;
@@ -134,12 +161,12 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.max_steps = c.max_steps;
 }
 
-int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int validate, const EvalOut &ev) {
-    // one request per CU (1024 threads) while that fits the chip, else several
-    int nt = c->cfg.planner_threads;
-    if (nt != 256 && nt != 1024) nt = nblk <= c->n_cu ? 1024 : 256;
+int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int validate, int epoch,
+                  const EvalOut &ev) {
+    const int nt = fmdp::kPlanThreads;
     HIP_TRY(hipEventRecord(c->e0, c->stream));
-    hipError_t e = fmdp::launch_planner(nblk, nt, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate, ev);
+    hipError_t e =
+        fmdp::launch_planner(nblk, nt, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate, epoch, ev);
     if (e != hipSuccess) {
         std::fprintf(stderr, "libfastmdp: planner launch failed: %s\n", hipGetErrorString(e));
         return FASTMDP_E_DEVICE;
@@ -158,9 +185,10 @@ void reset_stats(fastmdp_ctx *c) {
     c->st_ms = 0.0;
 }
 
-Slot fresh_slot(const fastmdp_request &r, int req_index) {
+Slot fresh_slot(const fastmdp_request &r, int req_index, int seq) {
     Slot s;
     std::memset(&s, 0, sizeof(s));
+    s.seq = seq;
     s.origin[0] = r.origin.x; s.origin[1] = r.origin.y; s.origin[2] = r.origin.z;
     s.goal[0] = r.goal.x; s.goal[1] = r.goal.y; s.goal[2] = r.goal.z;
     s.t0 = r.t0;
@@ -183,6 +211,52 @@ int copy_plan_out(fastmdp_ctx *c, int slot, const Slot &s, fastmdp_plan *out) {
     out->status = s.status;
     out->t0 = s.t0;
     out->n_points = n;
+    return 0;
+}
+
+// Copy the trajectories of accepted slots to the callers' plans: one gather
+// kernel into a device staging buffer, one copy into pinned host memory.
+int gather_plans_out(fastmdp_ctx *c, const std::vector<int> &slots, const std::vector<int> &reqs, const Slot *hs,
+                     fastmdp_plan *plans) {
+    const int m = (int)slots.size();
+    std::vector<long long> off(m);
+    long long total = 0;
+    for (int i = 0; i < m; ++i) {
+        const int n = hs[slots[i]].n_points;
+        if (plans[reqs[i]].capacity < n) return FASTMDP_E_CAPACITY;
+        off[i] = total;
+        total += n;
+    }
+    const size_t bytes = (size_t)total * (3 * sizeof(double) + sizeof(double) + sizeof(int));
+    if (bytes > c->gather_cap) {
+        const size_t cap = std::max(bytes, 2 * c->gather_cap);
+        hipFree(c->dGather);
+        if (c->hGather) hipHostFree(c->hGather);
+        c->dGather = c->hGather = nullptr;
+        c->gather_cap = 0;
+        if (hipMalloc(&c->dGather, cap) != hipSuccess || hipHostMalloc(&c->hGather, cap) != hipSuccess)
+            return FASTMDP_E_NOMEM;
+        c->gather_cap = cap;
+    }
+    HIP_TRY(hipMemcpyAsync(c->dList2, slots.data(), m * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->dOff, off.data(), m * sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(fmdp::launch_gather_traj(c->dSlots, c->dList2, m, c->dOff, total, c->tr, c->dGather, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->hGather, c->dGather, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double *xyz = static_cast<const double *>(c->hGather);
+    const double *val = xyz + 3 * total;
+    const int *act = reinterpret_cast<const int *>(val + total);
+    for (int i = 0; i < m; ++i) {
+        const Slot &s = hs[slots[i]];
+        fastmdp_plan &p = plans[reqs[i]];
+        const int n = s.n_points;
+        std::memcpy(p.xyz, xyz + 3 * off[i], (size_t)n * 3 * sizeof(double));
+        std::memcpy(p.action, act + off[i], (size_t)n * sizeof(int));
+        std::memcpy(p.value, val + off[i], (size_t)n * sizeof(double));
+        p.status = s.status;
+        p.t0 = s.t0;
+        p.n_points = n;
+    }
     return 0;
 }
 
@@ -213,6 +287,9 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->tb.X, tsz);
     rc = rc ? rc : dev_alloc(&c->tb.Y, tsz);
     rc = rc ? rc : dev_alloc(&c->tb.Z, tsz);
+    rc = rc ? rc : dev_alloc(&c->tb.vis, tsz);
+    rc = rc ? rc : dev_alloc(&c->tb.own, tsz);
+    rc = rc ? rc : dev_alloc(&c->tb.dead, tsz);
     rc = rc ? rc : dev_alloc(&c->tb.rowN, (size_t)cfg->max_rows);
     rc = rc ? rc : dev_alloc(&c->dSlots, (size_t)c->max_slots);
     rc = rc ? rc : dev_alloc(&c->dList, (size_t)c->max_slots);
@@ -223,10 +300,23 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->tr.val, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.seen, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.top, ssz);
+    rc = rc ? rc : dev_alloc(&c->tr.ep, ssz);
+    rc = rc ? rc : dev_alloc(&c->tr.col, ssz);
+    c->dl_cap = 1 << 22;
+    c->dl_start_cap = 1 << 16;
+    rc = rc ? rc : dev_alloc(&c->dDlRow, (size_t)c->dl_cap);
+    rc = rc ? rc : dev_alloc(&c->dDlCol, (size_t)c->dl_cap);
+    rc = rc ? rc : dev_alloc(&c->dDlEp, (size_t)c->dl_cap);
+    rc = rc ? rc : dev_alloc(&c->dDlLen, (size_t)1);
+    rc = rc ? rc : dev_alloc(&c->dDlStart, (size_t)c->dl_start_cap);
     rc = rc ? rc : dev_alloc(&c->dEv, (size_t)4 * c->A);
     rc = rc ? rc : dev_alloc(&c->dBest, (size_t)1);
     rc = rc ? rc : dev_alloc(&c->dPts, (size_t)c->stride * 3);
     rc = rc ? rc : dev_alloc(&c->dFlag, (size_t)1);
+    rc = rc ? rc : dev_alloc(&c->dList2, (size_t)c->max_slots);
+    rc = rc ? rc : dev_alloc(&c->dOff, (size_t)c->max_slots);
+    if (!rc && hipHostMalloc(reinterpret_cast<void **>(&c->hSlots), (size_t)c->max_slots * sizeof(Slot)) != hipSuccess)
+        rc = FASTMDP_E_NOMEM;
     if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
     if (!rc && hipEventCreate(&c->e0) != hipSuccess) rc = FASTMDP_E_DEVICE;
     if (!rc && hipEventCreate(&c->e1) != hipSuccess) rc = FASTMDP_E_DEVICE;
@@ -298,7 +388,7 @@ int fastmdp_load_plans(fastmdp_ctx *ctx, int32_t n, const int32_t *t0, const int
         hipError_t e = hipMemcpyAsync(dP, xyz, total * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(dR, rows.data(), total * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(dC, cols.data(), total * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
-        if (e == hipSuccess) e = fmdp::launch_scatter_points(ctx->tb, dP, dR, dC, (int)total, ctx->stream);
+        if (e == hipSuccess) e = fmdp::launch_scatter_points(ctx->tb, dP, dR, dC, (int)total, -1, ctx->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->tb.rowN, rowN.data(), rowN.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -341,11 +431,11 @@ int fastmdp_eval_step(fastmdp_ctx *ctx, const fastmdp_state *state, double *valu
     r.origin = state->pos;
     r.goal = state->goal;
     r.t0 = state->t;
-    Slot s = fresh_slot(r, 0);
+    Slot s = fresh_slot(r, 0, ctx->seq);
     HIP_TRY(hipMemcpyAsync(ctx->dSlots, &s, sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
     const int A = ctx->A;
     EvalOut ev{ctx->dEv, ctx->dEv + A, ctx->dEv + 2 * A, ctx->dEv + 3 * A, ctx->dBest};
-    int rc = timed_planner(ctx, 1, nullptr, 1, 0, ev);
+    int rc = timed_planner(ctx, 1, nullptr, 1, 0, 0, ev);
     if (rc) return rc;
     std::vector<double> h(4 * (size_t)A);
     int b = -1;
@@ -368,10 +458,10 @@ int fastmdp_plan_request(fastmdp_ctx *ctx, const fastmdp_request *req, fastmdp_p
     if (out->capacity < ctx->stride || !out->xyz || !out->action || !out->value) return FASTMDP_E_CAPACITY;
     std::lock_guard<std::mutex> lk(ctx->mu);
     reset_stats(ctx);
-    Slot s = fresh_slot(*req, 0);
+    Slot s = fresh_slot(*req, 0, ctx->seq);
     HIP_TRY(hipMemcpyAsync(ctx->dSlots, &s, sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
     EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
-    int rc = timed_planner(ctx, 1, nullptr, ctx->cfg.max_steps + 1, 0, none);
+    int rc = timed_planner(ctx, 1, nullptr, ctx->cfg.max_steps + 1, 0, 0, none);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(&s, ctx->dSlots, sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -393,8 +483,8 @@ int fastmdp_commit_plan(fastmdp_ctx *ctx, const fastmdp_plan *plan) {
         if (ctx->hRowN[t0 + k] >= ctx->tb.cap) return FASTMDP_E_CAPACITY;
     HIP_TRY(hipMemcpyAsync(ctx->dPts, plan->xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(fmdp::launch_fill_int(ctx->dFlag, 0, 1, ctx->stream));
-    HIP_TRY(fmdp::launch_commit_check(ctx->dc, ctx->tb, ctx->dPts, t0, n, ctx->dFlag, ctx->stream));
-    HIP_TRY(fmdp::launch_commit_append(ctx->tb, ctx->dPts, t0, n, ctx->dFlag, ctx->stream));
+    HIP_TRY(fmdp::launch_commit_check(ctx->dc, ctx->tb, ctx->dPts, t0, n, ctx->seq, ctx->dFlag, ctx->stream));
+    HIP_TRY(fmdp::launch_commit_append(ctx->tb, ctx->dPts, t0, n, ctx->seq, ctx->dFlag, ctx->stream));
     int flag = 0;
     HIP_TRY(hipMemcpyAsync(&flag, ctx->dFlag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -402,6 +492,7 @@ int fastmdp_commit_plan(fastmdp_ctx *ctx, const fastmdp_plan *plan) {
     if (flag) return FASTMDP_E_CONFLICT;
     for (int k = 0; k < n; ++k) ctx->hRowN[t0 + k] += 1;
     ctx->n_plans += 1;
+    ctx->seq += 1;
     return 0;
 }
 
@@ -423,12 +514,26 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
     auto now_s = [&]() { return std::chrono::duration<double>(clk::now() - t_start).count(); };
     const int S = std::min(ctx->max_slots, std::max(n, 1));
     const int budget = ctx->cfg.steps_per_launch > 0 ? ctx->cfg.steps_per_launch : 256;
-    std::vector<Slot> hs(S);
+    const int seq0 = ctx->seq;
+    Slot *hs = ctx->hSlots;                  // pinned mirror of the slots
     std::vector<int> slot_req(S, -1);        // request held by each slot
     std::vector<int> req_slot(n, -1);
     int next_req = 0, next_commit = 0;
-    std::vector<int> list, order;
-    std::vector<char> checked_since_commit(S, 0);   // slot already checked against the current table
+    std::vector<int> list;
+    // withdrawal log of this call: epoch e's withdrawals start at dl_start[e]
+    int epoch = 0, dl_len = 0;
+    std::vector<int> dl_start(2, 0);
+    HIP_TRY(fmdp::launch_fill_int(ctx->dDlLen, 0, 1, ctx->stream));
+    HIP_TRY(fmdp::launch_fill_int(ctx->dDlStart, 0, 2, ctx->stream));
+    DeathLog dl{ctx->dDlRow, ctx->dDlCol, ctx->dDlEp, ctx->dDlLen, ctx->dl_cap, ctx->dDlStart};
+    auto finish = [&](int rc) {
+        // the device row counts include tentative and withdrawn entries
+        if (hipMemcpyAsync(ctx->hRowN.data(), ctx->tb.rowN, ctx->hRowN.size() * sizeof(int), hipMemcpyDeviceToHost,
+                           ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return FASTMDP_E_DEVICE;
+        return rc;
+    };
     while (next_commit < n) {
         // admit arrived requests into free slots, in request order
         bool dirty = false;
@@ -436,13 +541,13 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
         for (int s = 0; s < S && next_req < n; ++s)
             if (slot_req[s] < 0) {
                 if (arrival_s && arrival_s[next_req] > t_now) break;
-                hs[s] = fresh_slot(reqs[next_req], next_req);
+                hs[s] = fresh_slot(reqs[next_req], next_req, seq0 + next_req);
                 slot_req[s] = next_req;
                 req_slot[next_req] = s;
                 ++next_req;
                 dirty = true;
             }
-        if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs.data(), S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+        if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
         // plan every running slot for up to `budget` steps
         list.clear();
         for (int s = 0; s < S; ++s)
@@ -457,57 +562,60 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
             EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
-            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, none);
-            if (rc) return rc;
-            HIP_TRY(hipMemcpyAsync(hs.data(), ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, epoch, none);
+            if (rc) return finish(rc);
+            HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipStreamSynchronize(ctx->stream));
         }
-        // every finished request goes to the sequencer in request order; the
-        // leading consecutive ones (from next_commit) may be accepted
-        order.clear();
-        int n_prefix = 0;
-        bool gap = false;
-        for (int r = next_commit; r < next_req; ++r) {
-            const int s = req_slot[r];
-            if (hs[s].status == fmdp::kRunning) { gap = true; continue; }
-            order.push_back(s);
-            if (!gap) ++n_prefix;
-        }
-        if (order.empty() || (n_prefix == 0 && !checked_since_commit.empty() &&
-                              std::all_of(order.begin(), order.end(), [&](int s) { return checked_since_commit[s]; })))
-            continue;
-        HIP_TRY(hipMemcpyAsync(ctx->dOrder, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice,
+        // pass over every finished, not yet accepted request
+        list.clear();
+        for (int r = next_commit; r < next_req; ++r)
+            if (hs[req_slot[r]].status != fmdp::kRunning) list.push_back(req_slot[r]);
+        if (list.empty()) continue;
+        epoch += 1;
+        if (epoch + 1 >= ctx->dl_start_cap) return finish(FASTMDP_E_CAPACITY);
+        dl_start.resize(epoch + 1);
+        dl_start[epoch] = dl_len;
+        HIP_TRY(hipMemcpyAsync(ctx->dDlStart + epoch, &dl_start[epoch], sizeof(int), hipMemcpyHostToDevice,
                                ctx->stream));
-        HIP_TRY(fmdp::launch_fcfs_sequencer(ctx->dc, ctx->tb, ctx->dSlots, ctx->dOrder, (int)order.size(), n_prefix,
-                                            ctx->tr, ctx->dNdone, ctx->stream));
-        int done = 0;
-        HIP_TRY(hipMemcpyAsync(&done, ctx->dNdone, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(hipMemcpyAsync(hs.data(), ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dList, (int)list.size(), ctx->tr, dl, epoch,
+                                       ctx->stream));
+        HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(&dl_len, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if (dl_len > ctx->dl_cap) return finish(FASTMDP_E_CAPACITY);
+        for (int s : list) {
+            if (hs[s].err) return finish(FASTMDP_E_CAPACITY);
+            if (hs[s].status == fmdp::kRunning) ctx->st_resumes += 1;
+        }
+        // accept in request order: a finished request whose predecessors are
+        // all accepted is final; one that withdrew entries in this pass ends
+        // the walk (later requests are checked against it next pass)
         const double t_done = now_s();
-        for (int s : order) checked_since_commit[s] = 1;
-        if (done > 0) std::fill(checked_since_commit.begin(), checked_since_commit.end(), 0);
-        for (int q = 0; q < done; ++q) {
-            const int s = order[q];
-            const int r = slot_req[s];
-            int rc = copy_plan_out(ctx, s, hs[s], &plans[r]);
-            if (rc) return rc;
-            committed[r] = hs[s].committed;
+        std::vector<int> acc_slots, acc_reqs;
+        while (next_commit < next_req) {
+            const int s = req_slot[next_commit];
+            if (hs[s].status == fmdp::kRunning) break;
+            const int r = next_commit;
+            committed[r] = (hs[s].status == FASTMDP_OK && hs[s].valid) ? 1 : 0;
             if (done_s) done_s[r] = t_done;
-            if (hs[s].committed) {
-                for (int k = 0; k < hs[s].n_points; ++k) ctx->hRowN[hs[s].t0 + k] += 1;
-                ctx->n_plans += 1;
-            }
+            ctx->n_plans += committed[r];
             ctx->st_pairs += hs[s].pairs;
             ctx->st_steps += hs[s].steps;
-            slot_req[s] = -1;
+            acc_slots.push_back(s);
+            acc_reqs.push_back(r);
             ++next_commit;
+            if (hs[s].killed) break;
         }
-        for (size_t q = done; q < order.size(); ++q)
-            if (hs[order[q]].status == fmdp::kRunning) ctx->st_resumes += 1;
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if (!acc_slots.empty()) {
+            int rc = gather_plans_out(ctx, acc_slots, acc_reqs, hs, plans);
+            if (rc) return finish(rc);
+            for (int s : acc_slots) slot_req[s] = -1;
+        }
     }
-    return 0;
+    ctx->seq = seq0 + n;
+    return finish(0);
 }
 
 int fastmdp_table_snapshot(fastmdp_ctx *ctx) {
@@ -544,30 +652,39 @@ int fastmdp_last_stats(const fastmdp_ctx *ctx, int64_t *pairs, int64_t *steps, i
     return 0;
 }
 
-// Checkpoint file: "FMDPTAB1", rows, cap, n_plans, rowN[rows], then for each
-// row its rowN entries of x, y and z (FP32).
+// Checkpoint file: "FMDPTAB2", rows, cap, n_plans, live entries per row
+// [rows], then for each row its live entries' x, y and z (FP32).  Withdrawn
+// entries are dropped; loaded entries are owned by no request.
 int fastmdp_save_table(fastmdp_ctx *ctx, const char *path) {
     if (!ctx || !path) return FASTMDP_E_INVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     const int rows = ctx->tb.rows, cap = ctx->tb.cap;
-    std::vector<float> buf((size_t)cap);
+    std::vector<int> dead((size_t)cap), live(rows, 0);
+    std::vector<float> buf[3];
+    for (auto &b : buf) b.resize((size_t)cap);
+    std::vector<std::vector<float>> keep(rows);
+    for (int r = 0; r < rows; ++r) {
+        const int m = std::min(ctx->hRowN[r], cap);
+        if (!m) continue;
+        const size_t off = (size_t)r * cap;
+        float *src[3] = {ctx->tb.X, ctx->tb.Y, ctx->tb.Z};
+        if (hipMemcpy(dead.data(), ctx->tb.dead + off, m * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            return FASTMDP_E_DEVICE;
+        for (int a = 0; a < 3; ++a)
+            if (hipMemcpy(buf[a].data(), src[a] + off, m * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+                return FASTMDP_E_DEVICE;
+        for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < m; ++j)
+                if (dead[j] == fmdp::kAlive) keep[r].push_back(buf[a][j]);
+        live[r] = (int)keep[r].size() / 3;
+    }
     FILE *f = std::fopen(path, "wb");
     if (!f) return FASTMDP_E_IO;
     int hdr[3] = {rows, cap, ctx->n_plans};
-    bool ok = std::fwrite("FMDPTAB1", 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int), 3, f) == 3 &&
-              std::fwrite(ctx->hRowN.data(), sizeof(int), rows, f) == (size_t)rows;
-    for (int r = 0; ok && r < rows; ++r) {
-        const int m = ctx->hRowN[r];
-        if (!m) continue;
-        float *src[3] = {ctx->tb.X, ctx->tb.Y, ctx->tb.Z};
-        for (int a = 0; a < 3 && ok; ++a) {
-            if (hipMemcpy(buf.data(), src[a] + (size_t)r * cap, m * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
-                std::fclose(f);
-                return FASTMDP_E_DEVICE;
-            }
-            ok = std::fwrite(buf.data(), sizeof(float), m, f) == (size_t)m;
-        }
-    }
+    bool ok = std::fwrite("FMDPTAB2", 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int), 3, f) == 3 &&
+              std::fwrite(live.data(), sizeof(int), rows, f) == (size_t)rows;
+    for (int r = 0; ok && r < rows; ++r)
+        if (!keep[r].empty()) ok = std::fwrite(keep[r].data(), sizeof(float), keep[r].size(), f) == keep[r].size();
     ok = (std::fclose(f) == 0) && ok;
     return ok ? 0 : FASTMDP_E_IO;
 }
@@ -579,13 +696,13 @@ int fastmdp_load_table(fastmdp_ctx *ctx, const char *path) {
     if (!f) return FASTMDP_E_IO;
     char magic[8];
     int hdr[3];
-    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "FMDPTAB1", 8) != 0 ||
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "FMDPTAB2", 8) != 0 ||
         std::fread(hdr, sizeof(int), 3, f) != 3) {
         std::fclose(f);
         return FASTMDP_E_IO;
     }
-    const int rows = hdr[0], cap = hdr[1];
-    if (rows != ctx->tb.rows || cap > ctx->tb.cap || hdr[2] < 0) {
+    const int rows = hdr[0];
+    if (rows != ctx->tb.rows || hdr[2] < 0) {
         std::fclose(f);
         return FASTMDP_E_CAPACITY;
     }
@@ -594,18 +711,33 @@ int fastmdp_load_table(fastmdp_ctx *ctx, const char *path) {
         std::fclose(f);
         return FASTMDP_E_IO;
     }
-    std::vector<float> buf((size_t)ctx->tb.cap);
+    for (int r = 0; r < rows; ++r)
+        if (rowN[r] < 0 || rowN[r] > ctx->tb.cap) {
+            std::fclose(f);
+            return FASTMDP_E_CAPACITY;
+        }
+    const int cap = ctx->tb.cap;
+    std::vector<float> buf((size_t)cap * 3);
+    std::vector<int> own((size_t)cap, -1), alive((size_t)cap, fmdp::kAlive);
     for (int r = 0; r < rows; ++r) {
         const int m = rowN[r];
-        if (m < 0 || m > ctx->tb.cap) { std::fclose(f); return FASTMDP_E_IO; }
+        if (!m) continue;
+        if (std::fread(buf.data(), sizeof(float), (size_t)m * 3, f) != (size_t)m * 3) {
+            std::fclose(f);
+            return FASTMDP_E_IO;
+        }
+        const size_t off = (size_t)r * cap;
         float *dst[3] = {ctx->tb.X, ctx->tb.Y, ctx->tb.Z};
-        for (int a = 0; a < 3 && m; ++a) {
-            if (std::fread(buf.data(), sizeof(float), m, f) != (size_t)m) { std::fclose(f); return FASTMDP_E_IO; }
-            if (hipMemcpy(dst[a] + (size_t)r * ctx->tb.cap, buf.data(), m * sizeof(float), hipMemcpyHostToDevice) !=
-                hipSuccess) {
-                std::fclose(f);
-                return FASTMDP_E_DEVICE;
-            }
+        bool ok = true;
+        for (int a = 0; a < 3 && ok; ++a)
+            ok = hipMemcpy(dst[a] + off, buf.data() + (size_t)a * m, m * sizeof(float), hipMemcpyHostToDevice) ==
+                 hipSuccess;
+        ok = ok && hipMemcpy(ctx->tb.vis + off, own.data(), m * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(ctx->tb.own + off, own.data(), m * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemcpy(ctx->tb.dead + off, alive.data(), m * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        if (!ok) {
+            std::fclose(f);
+            return FASTMDP_E_DEVICE;
         }
     }
     std::fclose(f);

@@ -9,9 +9,11 @@
 
 namespace fmdp {
 
-constexpr int kMaxActions = 1024;
+constexpr int kPlanThreads = 1024;  // planning workgroup: one request per CU, 16 wave64
+constexpr int kMaxActions = 512;
 constexpr int kMaxHeads = 128;
 constexpr int kRunning = -1;        // slot status while a request is being planned
+constexpr int kAlive = 0x7fffffff;  // table entry death epoch of a live entry
 constexpr double kBand = 1e-3;      // metres: FP32 nearest distances this close to the well
                                     // radius are recomputed exactly in FP64
 
@@ -22,6 +24,8 @@ struct DevCfg {
     double gamma, r_goal, r_intr, R_intr, gamma_intr, R_sep, r_terr, R_terr, gamma_terr;
     double log_gamma, log_gamma_intr, log_gamma_terr;   // discounts as exp(log_gamma * distance/ell)
     double abs_r_goal, abs_r_intr, abs_r_terr;
+    float log2_gamma_f, log2_gamma_intr_f, inv_ell_f;   // FP32 screening of the values
+    float abs_r_goal_f, abs_r_intr_f, R_intr2_f;
     double climb[FASTMDP_MAX_ACT_DIM], speed[FASTMDP_MAX_ACT_DIM];
     float kv[FASTMDP_MAX_ACT_DIM];       // -2 * speed * dt
     float climb_f[FASTMDP_MAX_ACT_DIM];  // climb rates
@@ -29,15 +33,23 @@ struct DevCfg {
     double tie_rel;
     double reach;                        // max(R_intr, R_sep) + 1 m: a plan farther than this from
                                          // a successor cannot change its value
+    double reach_state;                  // reach + longest action step: a plan farther than this
+                                         // from a state cannot change any of its successors' values
     int n_head, n_climb, n_speed, n_actions;
     int zero_climb;                      // index of the zero climb rate in the middle, else -1
     int max_steps;
 };
 
 // Time-major structure-of-arrays known-plan table.  Entry j of row t is at
-// [t * cap + j] in X, Y, Z; rowN[t] entries are in use, in commit order.
+// [t * cap + j] in X, Y, Z, vis, own, dead; rowN[t] entries are in use, in
+// append order.  own is the sequence number of the request that owns the
+// entry (-1 for loaded plans); dead is the epoch at which a tentative entry
+// was withdrawn (kAlive while it stands); vis is own while the entry stands
+// and kAlive once withdrawn, so that a request with sequence number q sees
+// exactly the entries with vis < q (the planner reads X, Y, Z, vis only).
 struct DevTable {
     float *X, *Y, *Z;
+    int *vis, *own, *dead;
     int *rowN;
     int cap, rows;
     const float *terr;                   // nullptr without terrain
@@ -55,22 +67,37 @@ struct Slot {
     long long pairs;  // pair evaluations, accumulated
     int steps;        // steps taken, accumulated
     int resume_at;    // FCFS check: first affected point, -1 if none
-    int committed;    // FCFS sequencer: 1 once appended to the table
+    int seq;          // sequence number: sees live table entries with own < seq
     int valid;        // OK trajectory passed the commit validation against the entries it saw
+    int killed;       // FCFS: withdrew tentative entries in the current pass
+    int err;          // FCFS: table or log capacity exceeded
+    int pad;
 };
 
 // Per-slot trajectory buffers, `stride` points per slot.  seen[k] is the
 // number of entries of the row scored to produce point k (for k = 0: the
-// departure row of the origin check).  top[k] is the action with the largest
-// value at that step when the chosen action (the lowest index inside the
-// tie band) is not itself the largest, else -1.
+// departure row of the origin check) and ep[k] the withdrawal epoch up to
+// which that scoring is known to be consistent.  top[k] is the action with
+// the largest value at that step when the chosen action (the lowest index
+// inside the tie band) is not itself the largest, else -1.  col[k] is the
+// column of point k's tentative table entry, -1 if none.
 struct Traj {
     double *xyz;
     int *act;
     double *val;
     int *seen;
+    int *ep;
     int *top;
+    int *col;
     int stride;
+};
+
+// Log of withdrawn table entries (row, column, epoch), in epoch order.
+struct DeathLog {
+    int *row, *col, *ep;
+    int *len;          // device counter
+    int cap;
+    const int *start;  // start[e]: log length when epoch e's withdrawals began
 };
 
 // Outputs of a single evaluated step (all device pointers, any may be null).
@@ -79,6 +106,12 @@ struct EvalOut {
     int *best;
 };
 
+// Entry j of a row (absolute index idx) is visible to the request with
+// sequence number seq.
+__device__ __forceinline__ bool entry_visible(const DevTable &tb, size_t idx, int seq) {
+    return tb.vis[idx] < seq;
+}
+
 // Squared distance, in FP64, between an FP64 point and an FP32 table entry:
 // the one separation arithmetic of the planner's exact checks and of commit.
 __device__ __forceinline__ double entry_d2(double x, double y, double z, float px, float py, float pz) {
@@ -86,20 +119,26 @@ __device__ __forceinline__ double entry_d2(double x, double y, double z, float p
     return dx * dx + dy * dy + dz * dz;
 }
 
-// nt: workgroup size, 256 (several requests per CU) or 1024 (one request per CU)
+// nt: workgroup size; kPlanThreads is the one built
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
-                          const int *list, const Traj &tr, int budget, int validate, const EvalOut &ev);
+                          const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev);
 bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
 
 // table.hip
 hipError_t launch_fill_int(int *p, int value, int n, hipStream_t st);
 hipError_t launch_scatter_points(const DevTable &t, const float *pts, const int *rows, const int *cols, int n,
-                                 hipStream_t st);
-hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double *pts, int t0, int n, int *flag,
-                               hipStream_t st);
-hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, const int *flag,
+                                 int own, hipStream_t st);
+hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double *pts, int t0, int n, int seq,
+                               int *flag, hipStream_t st);
+hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, int own, const int *flag,
                                 hipStream_t st);
-hipError_t launch_fcfs_sequencer(const DevCfg &c, const DevTable &t, Slot *slots, const int *order, int n_order,
-                                 int n_prefix, const Traj &tr, int *n_done, hipStream_t st);
+// Pack listed slots' trajectories (points from off[i]) into dst: total*3
+// doubles xyz, total doubles value, total ints action.
+hipError_t launch_gather_traj(const Slot *slots, const int *list, int n_list, const long long *off, long long total,
+                              const Traj &tr, void *dst, hipStream_t st);
+// FCFS pass over the finished, not yet accepted slots in `list`:
+// tentative insert, interaction check, withdrawal (see table.hip).
+hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, const int *list, int n_list,
+                            const Traj &tr, const DeathLog &dl, int epoch, hipStream_t st);
 
 }  // namespace fmdp

@@ -81,9 +81,21 @@ __device__ Scored score_action(const DevCfg &c, const DevTable &tb, int a, const
     return r;
 }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for its outstanding global loads (a plain __syncthreads
+// fence would also drain the prefetch of the next row).  Global data written
+// in the step loop is read back only after a full __syncthreads.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
     return v;
 }
 
@@ -99,24 +111,27 @@ __device__ __forceinline__ int wave_min(int v) {
 template <int NT>
 struct PlanGeom {
     static constexpr int NW = NT / 64;
-    static constexpr int TILE = NT >= 1024 ? 4096 : 2048;   // plans staged per LDS tile
-    static constexpr int PRE = TILE / NT;                    // row entries prefetched per thread
+    static constexpr int TILE = 4096;                        // row entries per chunk (LDS tile)
+    static constexpr int PRE = TILE / NT;                    // chunk entries per thread
 };
 
 template <int NT, int NC, int NV, int ZC>
 __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list,
-                                                     Traj tr, int budget, int validate, EvalOut ev) {
+                                                     Traj tr, int budget, int validate, int epoch, EvalOut ev) {
     using Geo = PlanGeom<NT>;
     constexpr int NW = Geo::NW, TILE = Geo::TILE, PRE = Geo::PRE;
     __shared__ float4 tile[TILE];               // staged plans; reused for the slice partial minima
-    __shared__ double sV[kMaxActions];
+    __shared__ double sV[kMaxActions];          // FP64 values of the candidate actions
     __shared__ double sD2[kMaxActions];         // squared nearest-plan distance per action
+    __shared__ float sLo[kMaxActions], sHi[kMaxActions];   // FP32 value brackets
     __shared__ double sC0[kMaxHeads], sS0[kMaxHeads];    // cos, sin of the heading offsets 2*pi*h/H
     __shared__ double sCos[kMaxHeads], sSin[kMaxHeads];  // heading directions of the current step
     __shared__ unsigned sBand[kMaxActions / 32];
     __shared__ double st_s[3];
     __shared__ int st_n, st_status, st_flag;
     __shared__ double red_d[NW];
+    __shared__ int s_wsum[NW];
+    __shared__ int s_any;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -129,12 +144,11 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     const int my_h = tid % H, my_slice = tid / H;
     const bool sweeper = tid < n_slices * H;
     const int tcap = (TILE / (2 * n_slices)) * (2 * n_slices);   // whole sweep rounds per tile
-    // slice partial minima: per wave after a shuffle reduction when a wave
-    // holds several lanes of one heading (H <= 64), else per slice
-    const int n_part = H <= 64 ? NW : n_slices;
+    const int n_part = n_slices;                                  // slice partial minima per action
 
     const double g[3] = {S.goal[0], S.goal[1], S.goal[2]};
     const int t0 = S.t0;
+    const int seq = S.seq;
     const size_t pt_base = (size_t)slot * tr.stride;
 
     for (int h = tid; h < H; h += NT) {
@@ -153,6 +167,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         st_n = n;
         st_status = kRunning;
         st_flag = 0;
+        s_any = 0;
     }
     __syncthreads();
 
@@ -160,11 +175,13 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     // no plan active at the departure row closer than R_sep.
     if (!eval && st_n == 0) {
         const double o[3] = {st_s[0], st_s[1], st_s[2]};
-        const int n_row = t0 < tb.rows ? tb.rowN[t0] : 0;
+        const int n_row = t0 < tb.rows ? min(tb.rowN[t0], tb.cap) : 0;
         const size_t rb = (size_t)t0 * tb.cap;
         int hit = 0;
         for (int j = tid; j < n_row; j += NT)
-            if (entry_d2(o[0], o[1], o[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < cfg.R_sep * cfg.R_sep) hit = 1;
+            if (entry_visible(tb, rb + j, seq) &&
+                entry_d2(o[0], o[1], o[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < cfg.R_sep * cfg.R_sep)
+                hit = 1;
         if (hit) st_flag = 1;        // benign race: every writer stores 1
         __syncthreads();
         if (tid == 0) {
@@ -175,7 +192,9 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             tr.act[pt_base] = -1;
             tr.val[pt_base] = 0.0;
             tr.seen[pt_base] = n_row;
+            tr.ep[pt_base] = epoch;
             tr.top[pt_base] = -1;
+            tr.col[pt_base] = -1;
             st_n = 1;
             if (blocked) st_status = FASTMDP_REJECT_ORIGIN;
         }
@@ -189,24 +208,74 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
 #pragma unroll
     for (int c = 0; c < NC; ++c) clf[c] = cfg.climb_f[c];
 
-    // first tile of the next row, prefetched into registers
+    // One chunk of a row (up to tcap entries) in registers: entry
+    // base + tid + i*NT with its visibility key, left unevaluated until
+    // staging so that the loads are not waited for where they are issued.
+    // The first chunk of the next step's row is loaded during the sweep
+    // (the barriers of the step loop do not wait for it).
     float px[PRE], py[PRE], pz[PRE];
+    int pk[PRE];
     int pre_n = 0;
-    auto prefetch = [&](int row) {
-        pre_n = (row >= 0 && row < tb.rows) ? tb.rowN[row] : 0;
-        const size_t rb = (size_t)(row < 0 ? 0 : row) * tb.cap;
-        const int lim = min(pre_n, tcap);
+    auto load_chunk = [&](int row, int base) {
+        const size_t rb = (size_t)row * tb.cap;
+        const int lim = min(pre_n - base, tcap);
 #pragma unroll
         for (int i = 0; i < PRE; ++i) {
             const int j = tid + i * NT;
+            pk[i] = kAlive;                                // invisible unless loaded
             if (j < lim) {
-                px[i] = tb.X[rb + j];
-                py[i] = tb.Y[rb + j];
-                pz[i] = tb.Z[rb + j];
+                const size_t idx = rb + base + j;
+                px[i] = tb.X[idx];
+                py[i] = tb.Y[idx];
+                pz[i] = tb.Z[idx];
+                pk[i] = tb.vis[idx];
             }
         }
     };
-    prefetch((eval ? t0 : t0 + st_n - 1) + 1);
+    auto row_count = [&](int row) { return (row >= 0 && row < tb.rows) ? min(tb.rowN[row], tb.cap) : 0; };
+    // Stage the chunk in registers into LDS, compacted to the entries this
+    // request sees, as (q_x, q_y, -2 dt q_z, |q|^2) with q = p - s; pad to
+    // whole sweep rounds with entries at infinity.  Returns the count.
+    auto stage_chunk = [&](const double s[3]) -> int {
+        bool pv[PRE];
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < PRE; ++i) {
+            pv[i] = pk[i] < seq;
+            cnt += pv[i] ? 1 : 0;
+        }
+        int x = cnt;                                       // inclusive wave scan
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        lds_barrier();
+        int pos = x - cnt, total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int t = s_wsum[w];
+            pos += w < wave ? t : 0;
+            total += t;
+        }
+#pragma unroll
+        for (int i = 0; i < PRE; ++i)
+            if (pv[i]) {
+                const float qx = (float)((double)px[i] - s[0]);
+                const float qy = (float)((double)py[i] - s[1]);
+                const float qz = (float)((double)pz[i] - s[2]);
+                tile[pos++] = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+            }
+        const int npad = ((total + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
+        for (int j = total + tid; j < npad; j += NT) tile[j] = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        return total;
+    };
+    {
+        const int row = (eval ? t0 : t0 + st_n - 1) + 1;
+        pre_n = row_count(row);
+        if (pre_n > 0) load_chunk(row, 0);
+    }
 
     long long pairs = 0;
     int steps_here = 0;
@@ -220,12 +289,12 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         if (!eval) {
             const double ex = g[0] - s[0], ey = g[1] - s[1], ez = g[2] - s[2];
             if (sqrt(ex * ex + ey * ey + ez * ez) <= cfg.ell) {
-                __syncthreads();
+                lds_barrier();
                 if (tid == 0) st_status = FASTMDP_OK;
                 break;
             }
             if (k >= cfg.max_steps) {
-                __syncthreads();
+                lds_barrier();
                 if (tid == 0) st_status = FASTMDP_TIMEOUT;
                 break;
             }
@@ -245,59 +314,36 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         const int row = t + 1;
         const int n_row = pre_n;
         const size_t rb = (size_t)row * tb.cap;
+        const int n_next = eval ? 0 : row_count(row + 1);   // used after staging: latency hidden
 
-        // 2. stage the first tile from the prefetched registers
-        {
-            const int nt = min(tcap, n_row);
-            const int npad = ((nt + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
-#pragma unroll
-            for (int i = 0; i < PRE; ++i) {
-                const int j = tid + i * NT;
-                if (j < npad) {
-                    float4 e = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
-                    if (j < nt) {
-                        const float qx = (float)((double)px[i] - s[0]);
-                        const float qy = (float)((double)py[i] - s[1]);
-                        const float qz = (float)((double)pz[i] - s[2]);
-                        e = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
-                    }
-                    tile[j] = e;
-                }
-            }
-        }
-        __syncthreads();
-
+        // 2-3. stage (compacted) and sweep the row chunk by chunk: every
+        //      lane, one heading's climb x speed actions over a slice of the
+        //      staged plans (two plans per round: v_min3)
         float ch = 0.0f, sh = 0.0f;
-        if (sweeper) {
-            ch = (float)sCos[my_h];
-            sh = (float)sSin[my_h];
-        }
         float acc[NC][NV];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[c][v] = INFINITY;
-
-        // 3. sweep: every lane, one heading's climb x speed actions over a
-        //    slice of the staged plans (two plans per round: v_min3)
+        const bool single = n_row <= tcap;
+        int n_vis = 0;
         for (int base = 0; base < n_row; base += tcap) {
-            const int nt = min(tcap, n_row - base);
-            const int npad = ((nt + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
             if (base > 0) {
-                __syncthreads();                           // previous tile fully swept
-                for (int j = tid; j < npad; j += NT) {
-                    float4 e = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
-                    if (j < nt) {
-                        const size_t idx = rb + base + j;
-                        const float qx = (float)((double)tb.X[idx] - s[0]);
-                        const float qy = (float)((double)tb.Y[idx] - s[1]);
-                        const float qz = (float)((double)tb.Z[idx] - s[2]);
-                        e = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
-                    }
-                    tile[j] = e;
-                }
-                __syncthreads();
+                lds_barrier();                             // previous chunk fully swept
+                load_chunk(row, base);
             }
+            const int nv = stage_chunk(s);
+            if (base == 0 && single && !eval) {            // next row in flight during the sweep
+                pre_n = n_next;
+                if (pre_n > 0) load_chunk(row + 1, 0);
+            }
+            n_vis += nv;
+            lds_barrier();
+            if (base == 0 && sweeper) {
+                ch = (float)sCos[my_h];
+                sh = (float)sSin[my_h];
+            }
+            const int npad = ((nv + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
             if (sweeper) {
                 for (int i = my_slice; i < npad; i += 2 * n_slices) {
                     const float4 p0 = tile[i];
@@ -318,43 +364,34 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 }
             }
         }
-        __syncthreads();                                   // tile is reused below
+        lds_barrier();                                   // tile is reused below
+        if (n_row == 0 && !eval) {
+            pre_n = n_next;
+            if (pre_n > 0) load_chunk(row + 1, 0);
+        }
 
-        // slice partial minima
+        // slice partial minima, one row of A per slice
         float *red = reinterpret_cast<float *>(tile);
-        if (H <= 64) {
-            // lanes l, l+H, l+2H, ... of a wave own the same heading
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    float m = acc[c][v];
-                    for (int off = H; off < 64; off += H) {
-                        const int src = lane + off < 64 ? lane + off : lane;
-                        m = fminf(m, __shfl(m, src));
-                    }
-                    acc[c][v] = m;
-                }
-            if (lane < H) {
-                const int h = (wave * 64 + lane) % H;
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) red[wave * A + (h * NC + c) * NV + v] = acc[c][v];
-            }
-        } else if (sweeper) {
+        if (sweeper) {
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) red[my_slice * A + (my_h * NC + c) * NV + v] = acc[c][v];
         }
         for (int w = tid; w < kMaxActions / 32; w += NT) sBand[w] = 0u;
-        __syncthreads();
+        lds_barrier();
 
-        // 4. per-action value.  The nearest-plan squared distance is
-        //    m + |Delta|^2 with m from the FP32 sweep; actions whose distance
-        //    lands within kBand of the well radius are flagged for an exact
-        //    FP64 recomputation so that well membership is decided in FP64.
+        // 4. per-action value, screened in FP32.  The nearest-plan squared
+        //    distance is m + |Delta|^2 with m from the FP32 sweep.  Each
+        //    action gets an FP32 bracket [lo, hi] of its value (1e-4 of the
+        //    terms it combines, far above the FP32 error); only actions whose
+        //    bracket reaches the largest lower bound can be chosen (or tie with
+        //    the choice) and are valued again in FP64 below.  Actions whose
+        //    nearest distance lands within kBand of the well radius get their
+        //    distance recomputed exactly in FP64 and are always valued in FP64,
+        //    so that well membership is decided in FP64.  The box and the
+        //    terrain clearance are decided in FP64.
+        const float gx32 = (float)(g[0] - s[0]), gy32 = (float)(g[1] - s[1]), gz32 = (float)(g[2] - s[2]);
         int band = 0;
         for (int a = tid; a < A; a += NT) {
             float m = INFINITY;
@@ -364,14 +401,42 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             const double step = cfg.speed[a % NV] * cfg.dt;
             const double dz = cfg.climb[(a / NV) % NC] * cfg.dt;
             const double d2 = (double)m + step * step + dz * dz;
-            sV[a] = score_action(cfg, tb, a, s, g, dx, dy, d2).V;
             sD2[a] = d2;
+            const double ox = step * dx, oy = step * dy;
+            float lo = -INFINITY, hi = -INFINITY;
+            if (!outside_box(cfg, s[0] + ox, s[1] + oy, s[2] + dz)) {
+                const float ex = gx32 - (float)ox, ey = gy32 - (float)oy, ez = gz32 - (float)dz;
+                const float G = cfg.abs_r_goal_f *
+                                exp2f(cfg.log2_gamma_f * (sqrtf(ex * ex + ey * ey + ez * ez) * cfg.inv_ell_f));
+                const float d2f = (float)d2;
+                float pen = 0.0f;
+                if (d2f < cfg.R_intr2_f)
+                    pen = cfg.abs_r_intr_f * exp2f(cfg.log2_gamma_intr_f * (sqrtf(fmaxf(d2f, 0.0f)) * cfg.inv_ell_f));
+                if (tb.terr) {
+                    const double clr = s[2] + dz - terrain_height(tb, s[0] + ox, s[1] + oy);
+                    if (clr < cfg.R_terr)
+                        pen = fmaxf(pen, (float)(cfg.abs_r_terr * exp(cfg.log_gamma_terr * (fmax(clr, 0.0) / cfg.ell))));
+                }
+                const float V = G - pen;
+                const float e = 1e-4f * (G + pen) + 1e-30f;
+                lo = V - e;
+                hi = V + e;
+            }
             if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) {
                 atomicOr(&sBand[a >> 5], 1u << (a & 31));
                 band = 1;
+                lo = -INFINITY;                            // valued in FP64 after the exact distance
+                hi = INFINITY;
             }
+            sLo[a] = lo;
+            sHi[a] = hi;
         }
-        if (__syncthreads_or(band)) {                      // uniform; almost never taken
+        if (band) s_any = 1;
+        lds_barrier();
+        const int any_band = s_any;
+        lds_barrier();
+        if (tid == 0) s_any = 0;                           // read by all before the reset
+        if (any_band) {                                    // uniform; almost never taken
             for (int w = 0; w < (A + 31) / 32; ++w) {
                 unsigned bits = sBand[w];
                 while (bits) {
@@ -383,17 +448,17 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     const double qz = s[2] + cfg.climb[(a / NV) % NC] * cfg.dt;
                     double dmin = INFINITY;
                     for (int j = tid; j < n_row; j += NT)
-                        dmin = fmin(dmin, entry_d2(qx, qy, qz, tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]));
+                        if (entry_visible(tb, rb + j, seq))
+                            dmin = fmin(dmin, entry_d2(qx, qy, qz, tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]));
                     dmin = -wave_max(-dmin);
                     if (lane == 0) red_d[wave] = dmin;
-                    __syncthreads();
+                    lds_barrier();
                     if (tid == 0) {
                         double d2 = red_d[0];
                         for (int q = 1; q < NW; ++q) d2 = fmin(d2, red_d[q]);
                         sD2[a] = d2;
-                        sV[a] = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], d2).V;
                     }
-                    __syncthreads();
+                    lds_barrier();
                 }
             }
         }
@@ -406,15 +471,28 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (ev.I) ev.I[a] = r.I;
                 if (ev.T) ev.T[a] = r.T;
             }
-        } else {
-            prefetch(row + 1);                             // in flight during the argmax and advance
+        } else if (!single) {
+            pre_n = n_next;                                // in flight during the argmax and advance
+            if (pre_n > 0) load_chunk(row + 1, 0);
         }
 
         // 5-6. argmax (one wave: largest value, then the lowest index inside
         //      the tie band) and advance
         if (wave == 0) {
+            float lb = -INFINITY;
+            for (int a = lane; a < A; a += 64) lb = fmaxf(lb, sLo[a]);
+            lb = wave_maxf(lb);
+            const float cut = lb - 1e-6f * fabsf(lb);
             double vm = -INFINITY;
-            for (int a = lane; a < A; a += 64) vm = fmax(vm, sV[a]);
+            for (int a = lane; a < A; a += 64) {
+                double v = -INFINITY;
+                if (eval || sHi[a] >= cut) {
+                    const int h = a / (NC * NV);
+                    v = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]).V;
+                }
+                sV[a] = v;
+                vm = fmax(vm, v);
+            }
             vm = wave_max(vm);
             const double thr = vm - cfg.tie_rel * fabs(vm);
             int li = 0x7fffffff;
@@ -432,6 +510,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 top = wave_min(ti);
             }
             if (lane == 0) {
+                pairs += (long long)A * n_vis;             // pairs with the plans this request sees
                 if (eval) {
                     if (ev.best) *ev.best = best;
                 } else if (best < 0) {
@@ -446,7 +525,9 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     tr.act[p] = best;
                     tr.val[p] = r.V;
                     tr.seen[p] = n_row;
+                    tr.ep[p] = epoch;
                     tr.top[p] = top;
+                    tr.col[p] = -1;
                     st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
                     st_n = n + 1;
                     if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
@@ -454,9 +535,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 }
             }
         }
-        pairs += (long long)A * n_row;
         steps_here += 1;
-        __syncthreads();
+        lds_barrier();
         if (eval) break;
     }
     __syncthreads();   // st_status written by thread 0 on the way out of the loop
@@ -475,7 +555,9 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             const int lim = tr.seen[pt_base + k];
             const size_t rb = (size_t)(t0 + k) * tb.cap;
             for (int j = tid; j < lim; j += NT)
-                if (entry_d2(x[0], x[1], x[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2) bad = 1;
+                if (entry_visible(tb, rb + j, seq) &&
+                    entry_d2(x[0], x[1], x[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2)
+                    bad = 1;
             if (tb.terr && (k % NT) == tid && x[2] - terrain_height(tb, x[0], x[1]) < 0.0) bad = 1;
         }
         bad = __syncthreads_or(bad);
@@ -497,21 +579,18 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
 // ---------------------------------------------------------------------------
 template <int NC, int NV, int ZC>
 static hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
-                           const int *list, const Traj &tr, int budget, int validate, const EvalOut &ev) {
-    if (nt == 1024)
-        hipLaunchKernelGGL((planner_kernel<1024, NC, NV, ZC>), dim3(nblk), dim3(1024), 0, st, c, t, s, list, tr, budget,
-                           validate, ev);
-    else
-        hipLaunchKernelGGL((planner_kernel<256, NC, NV, ZC>), dim3(nblk), dim3(256), 0, st, c, t, s, list, tr, budget,
-                           validate, ev);
+                           const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev) {
+    (void)nt;
+    hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC>), dim3(nblk), dim3(kPlanThreads), 0, st, c, t, s, list,
+                       tr, budget, validate, epoch, ev);
     return hipGetLastError();
 }
 
 #define FMDP_SHAPE(NC, NV, ZC) \
-    if (c.n_climb == NC && c.n_speed == NV && zc == ZC) return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, ev);
+    if (c.n_climb == NC && c.n_speed == NV && zc == ZC) return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, ev);
 
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
-                          const int *list, const Traj &tr, int budget, int validate, const EvalOut &ev) {
+                          const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev) {
     const int zc = c.zero_climb;
     FMDP_SHAPE(1, 1, 0) FMDP_SHAPE(1, 1, -1) FMDP_SHAPE(1, 2, 0) FMDP_SHAPE(1, 2, -1)
     FMDP_SHAPE(1, 3, 0) FMDP_SHAPE(1, 3, -1)

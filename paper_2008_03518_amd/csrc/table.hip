@@ -30,40 +30,46 @@ __global__ void fill_int_kernel(int *p, int value, int n) {
     if (i < n) p[i] = value;
 }
 
-__global__ void scatter_points_kernel(DevTable tb, const float *pts, const int *rows, const int *cols, int n) {
+__global__ void scatter_points_kernel(DevTable tb, const float *pts, const int *rows, const int *cols, int n,
+                                      int own) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const size_t idx = (size_t)rows[i] * tb.cap + cols[i];
     tb.X[idx] = pts[3 * i + 0];
     tb.Y[idx] = pts[3 * i + 1];
     tb.Z[idx] = pts[3 * i + 2];
+    tb.vis[idx] = own;
+    tb.own[idx] = own;
+    tb.dead[idx] = kAlive;
 }
 
 // Commit validation of one trajectory point as planned (FP64) against every
-// entry of its row as stored (FP32), in FP64; terrain clearance; capacity.
-// flag bit 0: conflict, bit 1: capacity.
-__device__ int check_point(const DevCfg &c, const DevTable &tb, const double p[3], int row, int tid, int nthr) {
+// entry of its row visible to `seq`, as stored (FP32), in FP64; terrain
+// clearance; capacity.  flag bit 0: conflict, bit 1: capacity.
+__device__ int check_point(const DevCfg &c, const DevTable &tb, const double p[3], int row, int seq, int tid,
+                           int nthr) {
     if (row >= tb.rows) return 2;
     const int n_row = tb.rowN[row];
     int f = n_row >= tb.cap ? 2 : 0;
     const double r2 = c.R_sep * c.R_sep;
     const size_t rb = (size_t)row * tb.cap;
     for (int j = tid; j < n_row; j += nthr)
-        if (entry_d2(p[0], p[1], p[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2) f |= 1;
+        if (entry_visible(tb, rb + j, seq) && entry_d2(p[0], p[1], p[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2)
+            f |= 1;
     if (tid == 0 && tb.terr && p[2] - table_terrain_height(tb, p[0], p[1]) < 0.0) f |= 1;
     return f;
 }
 
-__global__ void commit_check_kernel(DevCfg c, DevTable tb, const double *pts, int t0, int n, int *flag) {
+__global__ void commit_check_kernel(DevCfg c, DevTable tb, const double *pts, int t0, int n, int seq, int *flag) {
     const int k = blockIdx.x;
     if (k >= n) return;
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
-    const int f = check_point(c, tb, p, t0 + k, threadIdx.x, blockDim.x);
+    const int f = check_point(c, tb, p, t0 + k, seq, threadIdx.x, blockDim.x);
     if (f) atomicOr(flag, f);
 }
 
 // Append the trajectory rounded to FP32 (the table's storage format).
-__global__ void commit_append_kernel(DevTable tb, const double *pts, int t0, int n, const int *flag) {
+__global__ void commit_append_kernel(DevTable tb, const double *pts, int t0, int n, int own, const int *flag) {
     if (*flag) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -73,31 +79,102 @@ __global__ void commit_append_kernel(DevTable tb, const double *pts, int t0, int
     tb.X[idx] = (float)pts[3 * k + 0];
     tb.Y[idx] = (float)pts[3 * k + 1];
     tb.Z[idx] = (float)pts[3 * k + 2];
+    tb.vis[idx] = own;
+    tb.own[idx] = own;
+    tb.dead[idx] = kAlive;
     tb.rowN[row] = col + 1;
 }
 
-constexpr int kSeqThreads = 1024;
-constexpr int kCheckThreads = 256;
+// ---------------------------------------------------------------------------
+// First-come-first-served with concurrent requests and tentative plans.
+//
+// Request q (sequence number q) plans against the live table entries of
+// every earlier request: plans accepted before it and the tentative
+// trajectories of earlier requests that finished planning.  A finished
+// trajectory with status OK enters the table at once as tentative entries
+// owned by q; when q is re-planned from step k its entries from step k on are
+// withdrawn (dead = epoch, logged).  Passes run between planner launches; in
+// pass e (epoch e):
+//   1. insert: every finished OK trajectory enters the table (missing entries);
+//   2. check: every finished, not yet accepted trajectory is tested against
+//      the events since it scored each row:
+//        - added entries visible to it (entries [seen[k], rowN) of the row
+//          that produced point k): an added plan only adds a penalty, so
+//          every value at that step can only fall and the chosen action
+//          stays chosen with the same value unless the plan lands within the
+//          well radius of the chosen successor (or of the largest action's
+//          successor when the choice was made inside the tie band);
+//        - withdrawn entries it saw (logged deaths with epoch in
+//          (ep[k], e-1], column < seen[k], owner < q): a withdrawal can raise
+//          any successor's value, so it matters when within the well radius
+//          of any successor, i.e. within `reach_state` of the scored state;
+//        - for the origin (k = 0) the test is the origin check.
+//      The first affected step is recorded; clean steps take seen = rowN and
+//      ep = e - 1;
+//   3. withdraw: an affected trajectory drops its points from the first
+//      affected step on (their entries die with epoch e) and goes back to
+//      planning; a finished trajectory that is not OK (or failed its commit
+//      validation) withdraws all its entries.
+// Acceptance (host side) walks the requests in order: a finished request
+// whose checks are clean and all of whose predecessors are accepted is
+// final; its tentative entries simply stay.  A request that withdrew entries
+// in this pass ends the walk, because later requests have not yet been
+// checked against the withdrawal.
+// ---------------------------------------------------------------------------
+constexpr int kPassThreads = 256;
 
-// Interaction check of one finished trajectory against the table entries
-// appended after it scored their rows.  A plan committed after a row was
-// scored can only add penalties, so every action's value at that step can
-// only fall: the chosen action stays chosen, with the same value, unless the
-// new plan changes the chosen successor's own value (or, when the choice was
-// made inside the tie band, the largest action's value).  A new entry
-// (entries [seen[k], rowN) of the row that produced point k) can change a
-// successor's value only within the well radius of it; `reach` adds 1 m to
-// cover the planner's FP32 arithmetic.  For the origin (k = 0) the test is
-// the origin check.  Clean steps record the checked entries as seen.
-// Returns (through *first) the first affected point, untouched if none.
-__device__ void check_interactions(const DevCfg &c, const DevTable &tb, const Slot &S, const Traj &tr,
-                                   size_t base, int tid, int nthr, int *first) {
+__global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, Slot *slots, const int *list,
+                                                                   Traj tr) {
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    if (S.status != FASTMDP_OK || !S.valid) return;
+    const int n = S.n_points, t0 = S.t0, own = S.seq;
+    const size_t base = (size_t)slot * tr.stride;
+    int err = 0;
+    for (int k = threadIdx.x; k < n; k += kPassThreads) {
+        if (tr.col[base + k] >= 0) continue;
+        const int row = t0 + k;
+        if (row >= tb.rows) { err = 1; continue; }
+        const int col = atomicAdd(&tb.rowN[row], 1);
+        if (col >= tb.cap) {                          // row full: undo and report
+            atomicSub(&tb.rowN[row], 1);
+            err = 1;
+            continue;
+        }
+        const double *x = tr.xyz + (base + k) * 3;
+        const size_t idx = (size_t)row * tb.cap + col;
+        tb.X[idx] = (float)x[0];
+        tb.Y[idx] = (float)x[1];
+        tb.Z[idx] = (float)x[2];
+        tb.vis[idx] = own;
+        tb.own[idx] = own;
+        tb.dead[idx] = kAlive;
+        tr.col[base + k] = col;
+    }
+    if (err) S.err = 1;
+}
+
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                  const int *list, Traj tr, DeathLog dl,
+                                                                  int epoch) {
+    __shared__ int s_first, s_minep;
+    const int tid = threadIdx.x;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    const int n = S.n_points, t0 = S.t0, q = S.seq;
+    const size_t base = (size_t)slot * tr.stride;
+    if (tid == 0) { s_first = 0x7fffffff; s_minep = 0x7fffffff; }
+    __syncthreads();
+    int mine = 0x7fffffff;
+    for (int k = tid; k < n; k += kPassThreads) mine = min(mine, tr.ep[base + k]);
+    atomicMin(&s_minep, mine);
     const double r2 = c.reach * c.reach;
-    const int n = S.n_points, t0 = S.t0;
-    for (int k = tid; k < n; k += nthr) {
+
+    // added entries
+    for (int k = tid; k < n; k += kPassThreads) {
         const int row = t0 + k;
         if (row >= tb.rows) continue;
-        const int hi = tb.rowN[row];
+        const int hi = min(tb.rowN[row], tb.cap);
         const int lo = tr.seen[base + k];
         if (lo >= hi) continue;
         const double *x = tr.xyz + (base + k) * 3;     // chosen successor (the origin for k = 0)
@@ -119,108 +196,120 @@ __device__ void check_interactions(const DevCfg &c, const DevTable &tb, const Sl
             y[2] = sp[2] + c.climb[cl] * c.dt;
         }
         const size_t rb = (size_t)row * tb.cap;
-        bool hit = false;
         for (int j = lo; j < hi; ++j) {
+            if (!entry_visible(tb, rb + j, q)) continue;
             const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
             if (entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2) {
-                hit = true;
+                atomicMin(&s_first, k);
                 break;
             }
         }
-        if (hit) atomicMin(first, k);
-        else tr.seen[base + k] = hi;
     }
-}
-
-__device__ void resume_from(Slot &S, int first) {
-    S.resume_at = first;
-    S.n_points = first;          // keep points 0..first-1; re-score from point first-1
-    S.status = kRunning;
-    S.committed = 0;
-}
-
-// Every finished, not yet accepted slot against everything committed so far
-// (one workgroup per slot, in parallel).  An affected slot goes back to
-// planning from its first affected step at once, so that re-plans overlap.
-__global__ __launch_bounds__(kCheckThreads) void fcfs_check_kernel(DevCfg c, DevTable tb, Slot *slots,
-                                                                   const int *order, Traj tr) {
-    __shared__ int s_first;
-    const int slot = order[blockIdx.x];
-    Slot &S = slots[slot];
-    if (threadIdx.x == 0) s_first = 0x7fffffff;
     __syncthreads();
-    check_interactions(c, tb, S, tr, (size_t)slot * tr.stride, threadIdx.x, kCheckThreads, &s_first);
+
+    // withdrawn entries
+    const int minep = s_minep;
+    if (minep < epoch) {
+        const int lo = dl.start[minep + 1], hi = dl.start[epoch];
+        const double rs2 = c.reach_state * c.reach_state;
+        const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
+        for (int i = lo + tid; i < hi; i += kPassThreads) {
+            const int row = dl.row[i], col = dl.col[i], e = dl.ep[i];
+            const int k = row - t0;
+            if (k < 0 || k >= n) continue;
+            if (col >= tr.seen[base + k] || e <= tr.ep[base + k]) continue;
+            const size_t idx = (size_t)row * tb.cap + col;
+            if (tb.own[idx] >= q) continue;
+            const double *sp = tr.xyz + (base + (k == 0 ? 0 : k - 1)) * 3;
+            if (entry_d2(sp[0], sp[1], sp[2], tb.X[idx], tb.Y[idx], tb.Z[idx]) < (k == 0 ? ro2 : rs2))
+                atomicMin(&s_first, k);
+        }
+    }
     __syncthreads();
-    if (threadIdx.x == 0 && s_first != 0x7fffffff) resume_from(S, s_first);
+    const int first = s_first;
+    // steps before the first affected one are consistent with the table now
+    for (int k = tid; k < min(n, first); k += kPassThreads) {
+        const int row = t0 + k;
+        if (row < tb.rows) tr.seen[base + k] = min(tb.rowN[row], tb.cap);
+        tr.ep[base + k] = epoch - 1;
+    }
+    if (tid == 0) S.resume_at = first == 0x7fffffff ? -1 : first;
 }
 
-// Acceptance in request order of the leading slots (the first n_prefix
-// listed are consecutive requests; all were just checked against the table)
-// up to the first one that must be re-planned.  Each is checked against the
-// plans accepted earlier in this pass, then an OK trajectory that the
-// planning workgroup validated against the entries it saw (Slot::valid) is
-// appended if its rows have room.
-__global__ __launch_bounds__(kSeqThreads) void fcfs_accept_kernel(DevCfg c, DevTable tb, Slot *slots,
-                                                                  const int *order, int n_prefix, Traj tr,
-                                                                  int *n_done) {
-    __shared__ int s_first, s_flag;
+__global__ __launch_bounds__(kPassThreads) void fcfs_withdraw_kernel(DevTable tb, Slot *slots, const int *list,
+                                                                     Traj tr, DeathLog dl, int epoch) {
+    __shared__ int s_killed;
     const int tid = threadIdx.x;
-    int accepted = 0;                                      // uniform
-    for (int q = 0; q < n_prefix; ++q) {
-        Slot &S = slots[order[q]];
-        if (S.status == kRunning) break;                  // re-planned by the check pass
-        const int n = S.n_points;
-        const int t0 = S.t0;
-        const size_t base = (size_t)order[q] * tr.stride;
-        if (tid == 0) { s_first = 0x7fffffff; s_flag = 0; }
-        __syncthreads();
-        check_interactions(c, tb, S, tr, base, tid, kSeqThreads, &s_first);
-        __syncthreads();
-        if (s_first != 0x7fffffff) {
-            if (tid == 0) resume_from(S, s_first);
-            break;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    const int n = S.n_points, t0 = S.t0;
+    const size_t base = (size_t)slot * tr.stride;
+    int from = n;
+    if (S.resume_at >= 0) from = S.resume_at;
+    else if (S.status != FASTMDP_OK || !S.valid) from = 0;
+    if (tid == 0) s_killed = 0;
+    __syncthreads();
+    int killed = 0, err = 0;
+    for (int k = from + tid; k < n; k += kPassThreads) {
+        const int col = tr.col[base + k];
+        if (col < 0) continue;
+        const int row = t0 + k;
+        tb.dead[(size_t)row * tb.cap + col] = epoch;
+        tb.vis[(size_t)row * tb.cap + col] = kAlive;
+        const int i = atomicAdd(dl.len, 1);
+        if (i < dl.cap) {
+            dl.row[i] = row;
+            dl.col[i] = col;
+            dl.ep[i] = epoch;
+        } else {
+            err = 1;
         }
-        if (S.status == FASTMDP_OK && S.valid) {
-            // entries [0, seen[k]) were validated by the planning workgroup and
-            // the interaction checks cleared the rest; only capacity is left
-            if (tid == 0) s_flag = (t0 + n > tb.rows) ? 2 : 0;
-            __syncthreads();
-            for (int k = tid; k < n && s_flag == 0; k += kSeqThreads)
-                if (tb.rowN[t0 + k] >= tb.cap) atomicOr(&s_flag, 2);
-            __syncthreads();
-            const bool ok = s_flag == 0;
-            if (ok) {
-                for (int k = tid; k < n; k += kSeqThreads) {
-                    const int row = t0 + k;
-                    const int col = tb.rowN[row];
-                    const double *x = tr.xyz + (base + k) * 3;
-                    const size_t idx = (size_t)row * tb.cap + col;
-                    tb.X[idx] = (float)x[0];
-                    tb.Y[idx] = (float)x[1];
-                    tb.Z[idx] = (float)x[2];
-                    tb.rowN[row] = col + 1;
-                }
-            }
-            if (tid == 0) {
-                S.committed = ok ? 1 : 0;
-                S.resume_at = ok ? -1 : -3;   // -3: table capacity
-            }
-        } else if (S.status == FASTMDP_OK) {
-            if (tid == 0) {
-                S.committed = 0;
-                S.resume_at = -2;             // -2: refused by the commit validation
-            }
-        } else if (tid == 0) {
-            S.committed = 0;
-            S.resume_at = -1;
-        }
-        accepted = q + 1;
-        __syncthreads();
+        tr.col[base + k] = -1;
+        killed = 1;
     }
-    if (tid == 0) *n_done = accepted;
+    if (killed) s_killed = 1;
+    __syncthreads();
+    if (tid == 0) {
+        S.killed = s_killed;
+        if (err) S.err = 1;
+        if (S.resume_at >= 0) {
+            S.n_points = S.resume_at;   // keep points 0..resume_at-1; re-score from the last kept point
+            S.status = kRunning;
+            S.valid = 0;
+        }
+    }
+}
+
+// Pack the trajectories of the listed slots into one buffer for a single
+// device-to-host copy: slot list[i]'s n_points points go to point offset
+// off[i]; xyz (3 doubles), then action, then value per point, in three
+// contiguous sections of `total` points each.
+__global__ void gather_traj_kernel(const Slot *slots, const int *list, const long long *off, long long total, Traj tr,
+                                   double *xyz, int *act, double *val) {
+    const int slot = list[blockIdx.x];
+    const int n = slots[slot].n_points;
+    const long long o = off[blockIdx.x];
+    const size_t base = (size_t)slot * tr.stride;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        xyz[(o + k) * 3 + 0] = tr.xyz[(base + k) * 3 + 0];
+        xyz[(o + k) * 3 + 1] = tr.xyz[(base + k) * 3 + 1];
+        xyz[(o + k) * 3 + 2] = tr.xyz[(base + k) * 3 + 2];
+        act[o + k] = tr.act[base + k];
+        val[o + k] = tr.val[base + k];
+    }
 }
 
 }  // namespace
+
+hipError_t launch_gather_traj(const Slot *slots, const int *list, int n_list, const long long *off, long long total,
+                              const Traj &tr, void *dst, hipStream_t st) {
+    if (n_list <= 0) return hipSuccess;
+    double *xyz = static_cast<double *>(dst);
+    double *val = xyz + 3 * total;
+    int *act = reinterpret_cast<int *>(val + total);
+    hipLaunchKernelGGL(gather_traj_kernel, dim3(n_list), dim3(256), 0, st, slots, list, off, total, tr, xyz, act, val);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_int(int *p, int value, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
@@ -229,32 +318,32 @@ hipError_t launch_fill_int(int *p, int value, int n, hipStream_t st) {
 }
 
 hipError_t launch_scatter_points(const DevTable &t, const float *pts, const int *rows, const int *cols, int n,
-                                 hipStream_t st) {
+                                 int own, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_points_kernel, dim3((n + 255) / 256), dim3(256), 0, st, t, pts, rows, cols, n);
+    hipLaunchKernelGGL(scatter_points_kernel, dim3((n + 255) / 256), dim3(256), 0, st, t, pts, rows, cols, n, own);
     return hipGetLastError();
 }
 
-hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double *pts, int t0, int n, int *flag,
-                               hipStream_t st) {
+hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double *pts, int t0, int n, int seq,
+                               int *flag, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(commit_check_kernel, dim3(n), dim3(256), 0, st, c, t, pts, t0, n, flag);
+    hipLaunchKernelGGL(commit_check_kernel, dim3(n), dim3(256), 0, st, c, t, pts, t0, n, seq, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, const int *flag,
+hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, int own, const int *flag,
                                 hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(commit_append_kernel, dim3((n + 255) / 256), dim3(256), 0, st, t, pts, t0, n, flag);
+    hipLaunchKernelGGL(commit_append_kernel, dim3((n + 255) / 256), dim3(256), 0, st, t, pts, t0, n, own, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_fcfs_sequencer(const DevCfg &c, const DevTable &t, Slot *slots, const int *order, int n_order,
-                                 int n_prefix, const Traj &tr, int *n_done, hipStream_t st) {
-    if (n_order > 0)
-        hipLaunchKernelGGL(fcfs_check_kernel, dim3(n_order), dim3(kCheckThreads), 0, st, c, t, slots, order, tr);
-    hipLaunchKernelGGL(fcfs_accept_kernel, dim3(1), dim3(kSeqThreads), 0, st, c, t, slots, order, n_prefix, tr,
-                       n_done);
+hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, const int *list, int n_list,
+                            const Traj &tr, const DeathLog &dl, int epoch, hipStream_t st) {
+    if (n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fcfs_insert_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr);
+    hipLaunchKernelGGL(fcfs_check_kernel, dim3(n_list), dim3(kPassThreads), 0, st, c, t, slots, list, tr, dl, epoch);
+    hipLaunchKernelGGL(fcfs_withdraw_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr, dl, epoch);
     return hipGetLastError();
 }
 

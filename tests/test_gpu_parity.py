@@ -284,3 +284,45 @@ def test_fcfs_batch_equals_sequential(fm):
         assert c == cb, q
     assert _separation_violations(sc, plans, committed) == 0
     assert committed.sum() >= sc.requests.n // 2
+
+
+def test_serving_arrivals_equal_sequential(fm):
+    """Poisson arrivals (admitted as they arrive, planned while others are in
+    flight) give bitwise the sequential result; acceptance follows arrival."""
+    sc = S.large_actions(seed=13, n_plans=400, n_requests=40)
+    seq = []
+    with fm.context_for(sc) as ctx:
+        for q in range(sc.requests.n):
+            p = ctx.plan_request(sc.requests.origin[q], sc.requests.goal[q], 0)
+            seq.append((p, ctx.commit_plan(p) if p.status == 0 else False))
+    arr = S.serving_arrivals(400.0, sc.requests.n, seed=5)
+    with fm.context_for(sc, max_slots=32, steps_per_launch=64) as ctx:
+        plans, committed, done = ctx.plan_fcfs(sc.requests, arrival_s=arr)
+    for q, ((p, c), b, cb) in enumerate(zip(seq, plans, committed)):
+        assert p.status == b.status and np.array_equal(p.points(), b.points()), q
+        assert c == cb, q
+    assert np.all(done >= arr) and np.all(np.diff(done) >= 0)
+
+
+def test_fcfs_then_checkpoint(fm, tmp_path):
+    """After a concurrent batch the table holds exactly the accepted plans
+    (withdrawn tentative entries are not saved) and planning continues
+    identically from a reloaded checkpoint."""
+    sc = S.large_actions(seed=14, n_plans=300, n_requests=30)
+    path = str(tmp_path / "t.bin")
+    with fm.context_for(sc, max_slots=30) as ctx:
+        plans, committed, _ = ctx.plan_fcfs(sc.requests, limit=25)
+        assert ctx.n_plans == sc.plans.n + int(committed.sum())
+        ctx.save_table(path)
+        nxt = ctx.plan_request(sc.requests.origin[27], sc.requests.goal[27], 0)
+    live = int(sc.plans.length.sum()) + sum(p.n_points for p, c in zip(plans, committed) if c)
+    import struct
+    with open(path, "rb") as f:
+        f.read(8)
+        rows, cap, n_plans = struct.unpack("3i", f.read(12))
+        counts = np.frombuffer(f.read(4 * rows), dtype=np.int32)
+    assert int(counts.sum()) == live and n_plans == sc.plans.n + int(committed.sum())
+    with fm.Context(sc.cfg) as ctx2:
+        ctx2.load_table(path)
+        again = ctx2.plan_request(sc.requests.origin[27], sc.requests.goal[27], 0)
+    assert nxt.n_points == again.n_points and np.array_equal(nxt.points(), again.points())
