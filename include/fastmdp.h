@@ -18,11 +18,14 @@
  * Conventions shared by every entry point
  *   - Return value: 0 on success, a negative FASTMDP_E_* code on error.
  *     Nothing throws across this boundary.  fastmdp_strerror() names codes.
- *   - All pointers in signatures are HOST pointers.  The caller owns every
- *     input and output buffer and keeps them alive for the duration of the
- *     call; the context owns all device memory (known-plan table, terrain,
- *     per-request trajectories, scratch).  Every call is synchronous with
- *     respect to its outputs.
+ *   - Pointers in signatures are HOST pointers, except the training and
+ *     feature arrays of the learned action proposal, whose comments say
+ *     DEVICE (memory of the context's or the network's HIP device).  The
+ *     caller owns every input and output buffer and keeps them alive for
+ *     the duration of the call; the context owns all other device memory
+ *     (known-plan table, terrain, per-request trajectories, scratch), the
+ *     network its weights, optimiser state and activations.  Every call is
+ *     synchronous with respect to its outputs.
  *   - Calls on one context are serialised by the context; the order of
  *     fastmdp_commit_plan calls is the first-come-first-served order.
  *   - Units: metres, seconds, radians.  Positions are in the airspace box
@@ -212,6 +215,132 @@ int fastmdp_last_stats(const fastmdp_ctx *ctx, int64_t *pairs, int64_t *steps, i
  * Errors: E_IO, E_CAPACITY, E_DEVICE. */
 int fastmdp_save_table(fastmdp_ctx *ctx, const char *path);
 int fastmdp_load_table(fastmdp_ctx *ctx, const char *path);
+
+/* ------------------------------------------------------------------------
+ * Learned action proposal (an addition to the method, not in the paper).
+ *
+ * At each step a small network ranks the actions from features of the
+ * state; only the top_k are scored exactly (the same closed-form value as
+ * the full sweep), and the step is taken from them only when a certificate
+ * proves that no other action can reach the chosen value: every other
+ * action's value is at most its goal term (the penalties are
+ * non-negative), so if the best exact value among the k, less the argmax
+ * tie band, exceeds every other action's goal term, the full sweep would
+ * choose the same action.  Otherwise the step runs the full sweep.  Plans
+ * are therefore identical, bit for bit, to the plain method's.
+ *
+ * Features (FASTMDP_N_FEAT FP32 per state s at row t, goal g; plans are the
+ * entries of row t+1 the request sees, q = p - s):
+ *   [0,32)  per (sector k, half u): 1 - d/600 of the nearest plan with
+ *           d = |q| < 600 m, in sector k = floor((phi+pi)*16/(2 pi)) of the
+ *           bearing phi of q measured from the horizontal direction to the
+ *           goal (positive to the left), u = 0 if q_z >= 0 else 1;
+ *           index 2k+u; 0 if none;
+ *   [32,64) the count of such plans, clipped to 4, divided by 4;
+ *   64 horizontal distance to the goal / 10 km; 65 (g_z - s_z) / 500 m;
+ *   66 |g - s| / ell / 1000; 67 log(1 + |g - s|/ell) / 8; 68 s_z / 1000 m;
+ *   69-71 s_z, s_x, s_y scaled to [0,1] over the box; 72-73 the horizontal
+ *   unit vector to the goal; 74 min(n/16, 1) with n the plans within 600 m;
+ *   75 the nearest such distance / 600 (1 if none); 76-95 zero.
+ * Network: FASTMDP_N_FEAT -> n_hidden -> n_hidden -> n_out, ReLU, logits;
+ * BF16 weights and activations with FP32 accumulation; FP32 master weights
+ * trained with softmax cross-entropy on the chosen action and Adam.
+ * Parameters, packed FP32 in this order: W1 [n_hidden][n_in], b1 [n_hidden],
+ * W2 [n_hidden][n_hidden], b2 [n_hidden], W3 [n_out][n_hidden], b3 [n_out]
+ * (row-major, output index first). */
+#define FASTMDP_N_FEAT        96
+#define FASTMDP_MLP_HIDDEN   256   /* hidden width the planner's inference supports */
+#define FASTMDP_MAX_TOPK      16
+
+/* proposal modes (fastmdp_set_proposal) */
+#define FASTMDP_PROPOSE_NONE  0    /* full sweep at every step                       */
+#define FASTMDP_PROPOSE_MLP   1    /* the network's top_k logits                      */
+#define FASTMDP_PROPOSE_GOAL  2    /* the top_k goal terms (no network)               */
+
+typedef struct fastmdp_mlp fastmdp_mlp;
+
+/* Create a network on the current HIP device with zero parameters, for
+ * batches of up to max_batch rows.  n_in and n_hidden must be multiples of
+ * 32 (n_in = FASTMDP_N_FEAT for use by a planner); n_out >= 1.
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE. */
+int fastmdp_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch, fastmdp_mlp **out);
+
+/* Release the network.  NULL is a no-op.  A context using it for proposals
+ * must have its proposal reset first. */
+void fastmdp_mlp_destroy(fastmdp_mlp *net);
+
+/* Number of packed FP32 parameters (layout above). */
+int64_t fastmdp_mlp_num_params(const fastmdp_mlp *net);
+
+/* Copy all parameters in (HOST, packed FP32; resets the Adam state) or
+ * out.  Errors: E_INVAL, E_DEVICE. */
+int fastmdp_mlp_set_params(fastmdp_mlp *net, const float *params);
+int fastmdp_mlp_get_params(fastmdp_mlp *net, float *params);
+
+/* Logits of a batch: x DEVICE [batch][n_in] FP32, logits DEVICE
+ * [batch][n_out] FP32.  1 <= batch <= max_batch.  Errors: E_INVAL, E_DEVICE. */
+int fastmdp_mlp_forward(fastmdp_mlp *net, int32_t batch, const float *x, float *logits);
+
+/* Mean softmax cross-entropy of labels y (DEVICE [batch] int32 in
+ * [0, n_out)) and its gradient with respect to every parameter, written to
+ * grads (HOST, packed like the parameters); *loss (HOST) may be NULL.
+ * batch must be a multiple of 32.  Errors: E_INVAL, E_DEVICE. */
+int fastmdp_mlp_gradient(fastmdp_mlp *net, int32_t batch, const float *x, const int32_t *y, float *grads,
+                         float *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+ * size lr) on the gradient of the batch, as fastmdp_mlp_gradient defines
+ * it.  *loss (HOST, may be NULL) receives the batch loss before the step.
+ * batch must be a multiple of 32.  Errors: E_INVAL, E_DEVICE. */
+int fastmdp_mlp_train_step(fastmdp_mlp *net, int32_t batch, const float *x, const int32_t *y, float lr,
+                           float *loss);
+
+/* Proposal features (definition above) of n states against the table as a
+ * request with sequence number seqs[i] sees it: states and goals DEVICE
+ * [n][3] FP64, rows and seqs DEVICE [n] int32 (the plans are those of row
+ * rows[i] + 1), feat DEVICE [n][FASTMDP_N_FEAT] FP32.  Errors: E_INVAL,
+ * E_DEVICE. */
+int fastmdp_features(fastmdp_ctx *ctx, int32_t n, const double *states, const double *goals, const int32_t *rows,
+                     const int32_t *seqs, float *feat);
+
+/* Sequence number of the next request (the first of the next
+ * fastmdp_plan_fcfs call; request i of that call has this plus i). */
+int fastmdp_next_seq(const fastmdp_ctx *ctx);
+
+/* Select the proposal for later planning calls: mode FASTMDP_PROPOSE_*,
+ * 1 <= top_k <= FASTMDP_MAX_TOPK.  FASTMDP_PROPOSE_MLP needs a network with
+ * n_in = FASTMDP_N_FEAT, n_hidden = FASTMDP_MLP_HIDDEN and n_out >= the
+ * number of actions, on the same device; the context reads its current
+ * weights at every step, so it must stay alive (and untrained, if the plans
+ * are to be repeatable) while selected.  Errors: E_INVAL. */
+int fastmdp_set_proposal(fastmdp_ctx *ctx, int32_t mode, int32_t top_k, const fastmdp_mlp *net);
+
+/* The proposal at one state (as fastmdp_eval_step): features (HOST
+ * FASTMDP_N_FEAT) and logits (HOST, one per action), both
+ * FASTMDP_PROPOSE_MLP only (zero otherwise),
+ * the top_k proposed actions (HOST top_k, best first), whether the
+ * certificate held, and the action the proposal path takes (-1 when it
+ * falls back).  Any pointer may be NULL.  Errors: E_INVAL (no proposal
+ * selected), E_DEVICE. */
+int fastmdp_eval_proposal(fastmdp_ctx *ctx, const fastmdp_state *state, float *features, float *logits,
+                          int32_t *topk, int32_t *certified, int32_t *best);
+
+/* Steps of the last planning call that took the certified proposal path
+ * and that fell back to the full sweep.  Either pointer may be NULL. */
+int fastmdp_proposal_stats(const fastmdp_ctx *ctx, int64_t *certified, int64_t *fallbacks);
+
+/* Device memory for the DEVICE arguments above, for callers without an
+ * allocator of their own (memory of the current HIP device; copies are
+ * synchronous).  fastmdp_gather_rows copies n rows of row_bytes bytes:
+ * dst row i = src row idx[i], zero if idx[i] is not in [0, n_src) (dst,
+ * src, idx DEVICE; row_bytes a multiple of 4).  Errors: E_INVAL, E_NOMEM,
+ * E_DEVICE. */
+int fastmdp_device_alloc(int64_t bytes, void **ptr);
+int fastmdp_device_free(void *ptr);
+int fastmdp_copy_to_device(void *dst, const void *src, int64_t bytes);
+int fastmdp_copy_to_host(void *dst, const void *src, int64_t bytes);
+int fastmdp_gather_rows(void *dst, const void *src, int64_t n_src, const int64_t *idx, int64_t n,
+                        int32_t row_bytes);
 
 /* Static description of an error code or plan status (never NULL). */
 const char *fastmdp_strerror(int code);

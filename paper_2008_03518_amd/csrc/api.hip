@@ -57,9 +57,14 @@ struct fastmdp_ctx {
     void *dGather = nullptr, *hGather = nullptr;
     size_t gather_cap = 0;                // bytes
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    // learned action proposal
+    fmdp::PropArgs prop{};
+    float *dEvF = nullptr;        // proposal eval outputs: features, logits
+    int *dEvI = nullptr;          // top-k, certified, proposal's action
     std::mutex mu;
     // counters of the last call
     long long st_pairs = 0, st_steps = 0, st_resumes = 0, st_launches = 0;
+    long long st_hit = 0, st_miss = 0;
     double st_ms = 0.0;
 };
 
@@ -97,6 +102,7 @@ void free_all(fastmdp_ctx *c) {
     if (c->hSlots) hipHostFree(c->hSlots);
     if (c->hGather) hipHostFree(c->hGather);
     hipFree(c->dGather); hipFree(c->dList2); hipFree(c->dOff);
+    hipFree(c->dEvF); hipFree(c->dEvI);
     if (c->e0) hipEventDestroy(c->e0);
     if (c->e1) hipEventDestroy(c->e1);
     if (c->own) hipStreamDestroy(c->own);
@@ -165,8 +171,8 @@ int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int val
                   const EvalOut &ev) {
     const int nt = fmdp::kPlanThreads;
     HIP_TRY(hipEventRecord(c->e0, c->stream));
-    hipError_t e =
-        fmdp::launch_planner(nblk, nt, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate, epoch, ev);
+    hipError_t e = fmdp::launch_planner(nblk, nt, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate,
+                                        epoch, ev, c->prop);
     if (e != hipSuccess) {
         std::fprintf(stderr, "libfastmdp: planner launch failed: %s\n", hipGetErrorString(e));
         return FASTMDP_E_DEVICE;
@@ -182,6 +188,7 @@ int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int val
 
 void reset_stats(fastmdp_ctx *c) {
     c->st_pairs = c->st_steps = c->st_resumes = c->st_launches = 0;
+    c->st_hit = c->st_miss = 0;
     c->st_ms = 0.0;
 }
 
@@ -315,6 +322,8 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->dFlag, (size_t)1);
     rc = rc ? rc : dev_alloc(&c->dList2, (size_t)c->max_slots);
     rc = rc ? rc : dev_alloc(&c->dOff, (size_t)c->max_slots);
+    rc = rc ? rc : dev_alloc(&c->dEvF, (size_t)FASTMDP_N_FEAT + fmdp::kMaxActions);
+    rc = rc ? rc : dev_alloc(&c->dEvI, (size_t)FASTMDP_MAX_TOPK + 2);
     if (!rc && hipHostMalloc(reinterpret_cast<void **>(&c->hSlots), (size_t)c->max_slots * sizeof(Slot)) != hipSuccess)
         rc = FASTMDP_E_NOMEM;
     if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
@@ -470,6 +479,8 @@ int fastmdp_plan_request(fastmdp_ctx *ctx, const fastmdp_request *req, fastmdp_p
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->st_pairs = s.pairs;
     ctx->st_steps = s.steps;
+    ctx->st_hit = s.cert_hit;
+    ctx->st_miss = s.cert_miss;
     return 0;
 }
 
@@ -603,6 +614,8 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             ctx->n_plans += committed[r];
             ctx->st_pairs += hs[s].pairs;
             ctx->st_steps += hs[s].steps;
+            ctx->st_hit += hs[s].cert_hit;
+            ctx->st_miss += hs[s].cert_miss;
             acc_slots.push_back(s);
             acc_reqs.push_back(r);
             ++next_commit;
@@ -649,6 +662,77 @@ int fastmdp_last_stats(const fastmdp_ctx *ctx, int64_t *pairs, int64_t *steps, i
     if (resumes) *resumes = ctx->st_resumes;
     if (launches) *launches = ctx->st_launches;
     if (kernel_ms) *kernel_ms = ctx->st_ms;
+    return 0;
+}
+
+int fastmdp_features(fastmdp_ctx *ctx, int32_t n, const double *states, const double *goals, const int32_t *rows,
+                     const int32_t *seqs, float *feat) {
+    if (!ctx || n < 0 || (n > 0 && (!states || !goals || !rows || !seqs || !feat))) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIP_TRY(fmdp::launch_features(ctx->dc, ctx->tb, n, states, goals, rows, seqs, feat, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int fastmdp_next_seq(const fastmdp_ctx *ctx) { return ctx ? ctx->seq : FASTMDP_E_INVAL; }
+
+int fastmdp_set_proposal(fastmdp_ctx *ctx, int32_t mode, int32_t top_k, const fastmdp_mlp *net) {
+    if (!ctx) return FASTMDP_E_INVAL;
+    fmdp::PropArgs p{};
+    p.mode = mode;
+    p.k = top_k;
+    if (mode == FASTMDP_PROPOSE_NONE) {
+        p.k = 0;
+    } else if (mode == FASTMDP_PROPOSE_MLP || mode == FASTMDP_PROPOSE_GOAL) {
+        if (top_k < 1 || top_k > FASTMDP_MAX_TOPK || top_k > ctx->A) return FASTMDP_E_INVAL;
+        if (mode == FASTMDP_PROPOSE_MLP) {
+            if (fmdp::mlp_weights(net, &p.net)) return FASTMDP_E_INVAL;
+            if (p.net.n_in != FASTMDP_N_FEAT || p.net.n_hid != FASTMDP_MLP_HIDDEN || p.net.n_out < ctx->A)
+                return FASTMDP_E_INVAL;
+        }
+    } else {
+        return FASTMDP_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->prop = p;
+    return 0;
+}
+
+int fastmdp_eval_proposal(fastmdp_ctx *ctx, const fastmdp_state *state, float *features, float *logits,
+                          int32_t *topk, int32_t *certified, int32_t *best) {
+    if (!ctx || !state || state->t < 0) return FASTMDP_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->prop.mode == FASTMDP_PROPOSE_NONE) return FASTMDP_E_INVAL;
+    reset_stats(ctx);
+    fastmdp_request r{};
+    r.origin = state->pos;
+    r.goal = state->goal;
+    r.t0 = state->t;
+    Slot s = fresh_slot(r, 0, ctx->seq);
+    HIP_TRY(hipMemcpyAsync(ctx->dSlots, &s, sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->dEvF, 0, (FASTMDP_N_FEAT + fmdp::kMaxActions) * sizeof(float), ctx->stream));
+    const int A = ctx->A;
+    EvalOut ev{nullptr, nullptr, nullptr, nullptr, ctx->dBest, ctx->dEvF, ctx->dEvF + FASTMDP_N_FEAT,
+               ctx->dEvI, ctx->dEvI + FASTMDP_MAX_TOPK, ctx->dEvI + FASTMDP_MAX_TOPK + 1};
+    int rc = timed_planner(ctx, 1, nullptr, 1, 0, 0, ev);
+    if (rc) return rc;
+    std::vector<float> hf(FASTMDP_N_FEAT + (size_t)A);
+    int hi[FASTMDP_MAX_TOPK + 2];
+    HIP_TRY(hipMemcpyAsync(hf.data(), ctx->dEvF, hf.size() * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(hi, ctx->dEvI, sizeof(hi), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (features) std::memcpy(features, hf.data(), FASTMDP_N_FEAT * sizeof(float));
+    if (logits) std::memcpy(logits, hf.data() + FASTMDP_N_FEAT, A * sizeof(float));
+    if (topk) std::memcpy(topk, hi, ctx->prop.k * sizeof(int));
+    if (certified) *certified = hi[FASTMDP_MAX_TOPK];
+    if (best) *best = hi[FASTMDP_MAX_TOPK + 1];
+    return 0;
+}
+
+int fastmdp_proposal_stats(const fastmdp_ctx *ctx, int64_t *certified, int64_t *fallbacks) {
+    if (!ctx) return FASTMDP_E_INVAL;
+    if (certified) *certified = ctx->st_hit;
+    if (fallbacks) *fallbacks = ctx->st_miss;
     return 0;
 }
 

@@ -71,6 +71,8 @@ struct Slot {
     int valid;        // OK trajectory passed the commit validation against the entries it saw
     int killed;       // FCFS: withdrew tentative entries in the current pass
     int err;          // FCFS: table or log capacity exceeded
+    int cert_hit;     // proposal steps certified, accumulated
+    int cert_miss;    // proposal steps that fell back to the full sweep, accumulated
     int pad;
 };
 
@@ -101,9 +103,26 @@ struct DeathLog {
 };
 
 // Outputs of a single evaluated step (all device pointers, any may be null).
+// feat, logit, topk, cert and pbest are written only with a proposal.
 struct EvalOut {
     double *V, *G, *I, *T;
     int *best;
+    float *feat, *logit;
+    int *topk, *cert, *pbest;
+};
+
+// Proposal network weights as the planner reads them: BF16 [out][in]
+// (W3 zero-padded to a multiple of 32 rows), FP32 biases.
+struct PropNet {
+    const uint16_t *W1, *W2, *W3;
+    const float *b1, *b2, *b3;
+    int n_in, n_hid, n_out;
+};
+
+// Proposal selection of a planner launch (mode FASTMDP_PROPOSE_*).
+struct PropArgs {
+    int mode, k;
+    PropNet net;
 };
 
 // Entry j of a row (absolute index idx) is visible to the request with
@@ -119,10 +138,20 @@ __device__ __forceinline__ double entry_d2(double x, double y, double z, float p
     return dx * dx + dy * dy + dz * dz;
 }
 
-// nt: workgroup size; kPlanThreads is the one built
+// nt: workgroup size; kPlanThreads is the one built.  prop.mode selects the
+// proposal path (FASTMDP_PROPOSE_NONE: full sweep only).
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
-                          const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev);
+                          const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
+                          const PropArgs &prop);
 bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
+
+// features.hip: proposal features of n states (device arrays, see
+// fastmdp_features).
+hipError_t launch_features(const DevCfg &c, const DevTable &t, int n, const double *states, const double *goals,
+                           const int *rows, const int *seqs, float *feat, hipStream_t st);
+
+// mlp.hip: the planner's view of a network's weights.
+int mlp_weights(const fastmdp_mlp *m, PropNet *w);
 
 // table.hip
 hipError_t launch_fill_int(int *p, int value, int n, hipStream_t st);

@@ -22,6 +22,7 @@
 //   6. state advance, goal capture, collision checks and trajectory append
 //      ("Determine terminal state").
 #include "planner.h"
+#include "proposal.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -55,19 +56,42 @@ struct Scored {
     double clr;         // terrain clearance (inf without terrain)
 };
 
+// Successor of state s under action a, whose heading has unit direction
+// (dx, dy).
+__device__ __forceinline__ void successor(const DevCfg &c, int a, const double s[3], double dx, double dy, double &x,
+                                          double &y, double &z) {
+    const int v = a % c.n_speed;
+    const int cl = (a / c.n_speed) % c.n_climb;
+    const double step = c.speed[v] * c.dt;
+    x = s[0] + step * dx;
+    y = s[1] + step * dy;
+    z = s[2] + c.climb[cl] * c.dt;
+}
+
+// Goal peak r_goal * gamma^(d/ell) at a successor.  Every action's value is
+// at most this term (the penalties are non-negative), the bound the
+// proposal certificate rests on; both use this one function.
+__device__ __forceinline__ double goal_term(const DevCfg &c, double x, double y, double z, const double g[3]) {
+    const double ex = g[0] - x, ey = g[1] - y, ez = g[2] - z;
+    return c.abs_r_goal * exp(c.log_gamma * (sqrt(ex * ex + ey * ey + ez * ez) / c.ell));
+}
+
+// Squared distance from action a's successor to the nearest plan, from the
+// sweep's minimum m of |q|^2 - 2 Delta . q over the staged plans.
+template <int NC, int NV>
+__device__ __forceinline__ double nearest_d2(const DevCfg &c, int a, float m) {
+    const double step = c.speed[a % NV] * c.dt;
+    const double dz = c.climb[(a / NV) % NC] * c.dt;
+    return fma(dz, dz, fma(step, step, (double)m));
+}
+
 // Score action a from state s: dx, dy is its heading's unit direction and
 // d2 the squared distance from the successor to the nearest plan.
 __device__ Scored score_action(const DevCfg &c, const DevTable &tb, int a, const double s[3], const double g[3],
                                double dx, double dy, double d2) {
     Scored r;
-    const int v = a % c.n_speed;
-    const int cl = (a / c.n_speed) % c.n_climb;
-    const double step = c.speed[v] * c.dt;
-    r.x = s[0] + step * dx;
-    r.y = s[1] + step * dy;
-    r.z = s[2] + c.climb[cl] * c.dt;
-    const double ex = g[0] - r.x, ey = g[1] - r.y, ez = g[2] - r.z;
-    r.G = c.abs_r_goal * exp(c.log_gamma * (sqrt(ex * ex + ey * ey + ez * ez) / c.ell));
+    successor(c, a, s, dx, dy, r.x, r.y, r.z);
+    r.G = goal_term(c, r.x, r.y, r.z, g);
     r.I = 0.0;
     if (d2 < c.R_intr * c.R_intr) r.I = c.abs_r_intr * exp(c.log_gamma_intr * (sqrt(fmax(d2, 0.0)) / c.ell));
     r.T = 0.0;
@@ -115,11 +139,13 @@ struct PlanGeom {
     static constexpr int PRE = TILE / NT;                    // chunk entries per thread
 };
 
-template <int NT, int NC, int NV, int ZC>
+template <int NT, int NC, int NV, int ZC, bool PROP>
 __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list,
-                                                     Traj tr, int budget, int validate, int epoch, EvalOut ev) {
+                                                     Traj tr, int budget, int validate, int epoch, EvalOut ev,
+                                                     PropArgs prop) {
     using Geo = PlanGeom<NT>;
     constexpr int NW = Geo::NW, TILE = Geo::TILE, PRE = Geo::PRE;
+    constexpr int KMAX = FASTMDP_MAX_TOPK, HID = FASTMDP_MLP_HIDDEN;
     __shared__ float4 tile[TILE];               // staged plans; reused for the slice partial minima
     __shared__ double sV[kMaxActions];          // FP64 values of the candidate actions
     __shared__ double sD2[kMaxActions];         // squared nearest-plan distance per action
@@ -132,6 +158,15 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ double red_d[NW];
     __shared__ int s_wsum[NW];
     __shared__ int s_any;
+    // proposal path only
+    __shared__ FeatAcc sFa;                                      // traffic feature accumulators
+    __shared__ __attribute__((aligned(16))) uint16_t sAct[3][HID];   // BF16 features, hidden 1, hidden 2
+    __shared__ float sKey[kMaxActions];                          // ranking key per action
+    __shared__ double sG[kMaxActions];                           // goal-term bound per action
+    __shared__ unsigned sInK[kMaxActions / 32];                  // proposed-set membership
+    __shared__ int sK[KMAX];                                     // proposed actions, best first
+    __shared__ float sKm[NW][KMAX];                              // per-wave nearest minima
+    __shared__ int st_cert, st_best, st_top;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -156,6 +191,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         sC0[h] = cos(th);
         sS0[h] = sin(th);
     }
+    if constexpr (PROP) feat_reset(sFa, tid);
     if (tid == 0) {
         const int n = eval ? 0 : S.n_points;
         if (n == 0) {
@@ -271,6 +307,35 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         for (int j = total + tid; j < npad; j += NT) tile[j] = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
         return total;
     };
+    // Actions whose FP32 nearest distance lies within kBand of the well
+    // radius (flagged in sBand) get it recomputed exactly in FP64 over the
+    // visible entries of the row.  Uniform: every thread calls it.
+    auto band_recheck = [&](const double s[3], int n_row, size_t rb) {
+        for (int w = 0; w < (A + 31) / 32; ++w) {
+            unsigned bits = sBand[w];
+            while (bits) {
+                const int a = w * 32 + __builtin_ctz(bits);
+                bits &= bits - 1;
+                const int h = a / (NC * NV);
+                const double step = cfg.speed[a % NV] * cfg.dt;
+                const double qx = s[0] + step * sCos[h], qy = s[1] + step * sSin[h];
+                const double qz = s[2] + cfg.climb[(a / NV) % NC] * cfg.dt;
+                double dmin = INFINITY;
+                for (int j = tid; j < n_row; j += NT)
+                    if (entry_visible(tb, rb + j, seq))
+                        dmin = fmin(dmin, entry_d2(qx, qy, qz, tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]));
+                dmin = -wave_max(-dmin);
+                if (lane == 0) red_d[wave] = dmin;
+                lds_barrier();
+                if (tid == 0) {
+                    double d2 = red_d[0];
+                    for (int q = 1; q < NW; ++q) d2 = fmin(d2, red_d[q]);
+                    sD2[a] = d2;
+                }
+                lds_barrier();
+            }
+        }
+    };
     {
         const int row = (eval ? t0 : t0 + st_n - 1) + 1;
         pre_n = row_count(row);
@@ -278,7 +343,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     }
 
     long long pairs = 0;
-    int steps_here = 0;
+    int steps_here = 0, hits = 0, misses = 0;
 
     for (;;) {
         if (st_status != kRunning) break;                 // uniform (LDS, after a barrier)
@@ -302,237 +367,426 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         }
 
         // 1. heading directions: the goal bearing rotated by each offset
-        {
-            const double bx = g[0] - s[0], by = g[1] - s[1];
-            const double r = sqrt(bx * bx + by * by);
-            const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
-            for (int h = tid; h < H; h += NT) {
-                sCos[h] = cb * sC0[h] - sb * sS0[h];
-                sSin[h] = sb * sC0[h] + cb * sS0[h];
-            }
+        const double bx = g[0] - s[0], by = g[1] - s[1];
+        const double br = sqrt(bx * bx + by * by);
+        const double cb = br > 0.0 ? bx / br : 1.0, sb = br > 0.0 ? by / br : 0.0;
+        for (int h = tid; h < H; h += NT) {
+            sCos[h] = cb * sC0[h] - sb * sS0[h];
+            sSin[h] = sb * sC0[h] + cb * sS0[h];
         }
         const int row = t + 1;
         const int n_row = pre_n;
         const size_t rb = (size_t)row * tb.cap;
         const int n_next = eval ? 0 : row_count(row + 1);   // used after staging: latency hidden
-
-        // 2-3. stage (compacted) and sweep the row chunk by chunk: every
-        //      lane, one heading's climb x speed actions over a slice of the
-        //      staged plans (two plans per round: v_min3)
-        float ch = 0.0f, sh = 0.0f;
-        float acc[NC][NV];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[c][v] = INFINITY;
         const bool single = n_row <= tcap;
+
         int n_vis = 0;
-        for (int base = 0; base < n_row; base += tcap) {
-            if (base > 0) {
-                lds_barrier();                             // previous chunk fully swept
-                load_chunk(row, base);
-            }
-            const int nv = stage_chunk(s);
-            if (base == 0 && single && !eval) {            // next row in flight during the sweep
-                pre_n = n_next;
-                if (pre_n > 0) load_chunk(row + 1, 0);
-            }
-            n_vis += nv;
-            lds_barrier();
-            if (base == 0 && sweeper) {
-                ch = (float)sCos[my_h];
-                sh = (float)sSin[my_h];
-            }
-            const int npad = ((nv + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
-            if (sweeper) {
-                for (int i = my_slice; i < npad; i += 2 * n_slices) {
-                    const float4 p0 = tile[i];
-                    const float4 p1 = tile[i + n_slices];
-                    const float hq0 = fmaf(p0.x, ch, p0.y * sh);
-                    const float hq1 = fmaf(p1.x, ch, p1.y * sh);
+        bool staged = false;
+        int cert = 0;
+        // Proposal path (rows that fit one tile): rank the actions, score the
+        // top k exactly with the full sweep's arithmetic, and take the step
+        // from them when the certificate holds.
+        if constexpr (PROP) {
+            if (prop.mode != FASTMDP_PROPOSE_NONE && single) {
+                if (n_row > 0) n_vis = stage_chunk(s);
+                if (!eval) {                               // next row in flight meanwhile
+                    pre_n = n_next;
+                    if (pre_n > 0) load_chunk(row + 1, 0);
+                }
+                staged = true;
+                const int K = min(prop.k, A);
+                if (n_row == 0) lds_barrier();             // headings visible (staging has its own barrier)
+                // goal-term bound of every action (-inf outside the box)
+                for (int a = tid; a < A; a += NT) {
+                    const int h = a / (NC * NV);
+                    double x, y, z;
+                    successor(cfg, a, s, sCos[h], sSin[h], x, y, z);
+                    const double G = outside_box(cfg, x, y, z) ? -INFINITY : goal_term(cfg, x, y, z, g);
+                    sG[a] = G;
+                    if (prop.mode == FASTMDP_PROPOSE_GOAL) sKey[a] = (float)G;
+                }
+                for (int w = tid; w < kMaxActions / 32; w += NT) sInK[w] = 0u;
+                lds_barrier();                             // tile staged, headings visible
+                if (prop.mode == FASTMDP_PROPOSE_MLP) {
+                    const float ux = (float)cb, uy = (float)sb;
+                    for (int j = tid; j < n_vis; j += NT) {
+                        const float4 p = tile[j];
+                        feat_point(sFa, p.x, p.y, p.z <= 0.0f, p.w, ux, uy);
+                    }
+                    lds_barrier();
+                    if (tid < FASTMDP_N_FEAT) {
+                        const float f = feat_value(sFa, tid, s, g, cfg.box_lo, cfg.box_hi, cfg.ell);
+                        sAct[0][tid] = f2bf(f);
+                        if (ev.feat) ev.feat[tid] = f;
+                    }
+                    lds_barrier();
+                    feat_reset(sFa, tid);                  // next use is several barriers away
+                    // three layers, one 16-neuron tile per wave at a time:
+                    // the state vector is broadcast to every row of the MFMA A
+                    // operand, the weights [out][in] are the B operand, row 0
+                    // of the result (lanes 0-15, register 0) is the layer.
+                    const PropNet &W = prop.net;
+                    for (int layer = 0; layer < 3; ++layer) {
+                        const int kin = layer == 0 ? FASTMDP_N_FEAT : HID;
+                        const int nout = layer == 2 ? A : HID;
+                        const uint16_t *Wl = layer == 0 ? W.W1 : (layer == 1 ? W.W2 : W.W3);
+                        const float *bl = layer == 0 ? W.b1 : (layer == 1 ? W.b2 : W.b3);
+                        const uint16_t *in = sAct[layer];
+                        for (int tl = wave; tl * 16 < nout; tl += NW) {
+                            const int nn = tl * 16 + (lane & 15);
+                            const int kofs = 8 * (lane >> 4);
+                            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                            for (int k0 = 0; k0 < kin; k0 += 32) {
+                                const uint4 av = *reinterpret_cast<const uint4 *>(in + k0 + kofs);
+                                const uint4 wv = *reinterpret_cast<const uint4 *>(Wl + (size_t)nn * kin + k0 + kofs);
+                                acc = mfma_bf16(av, wv, acc);
+                            }
+                            if (lane < 16 && nn < nout) {
+                                const float z = acc[0] + bl[nn];
+                                if (layer < 2) {
+                                    sAct[layer + 1][nn] = f2bf(fmaxf(z, 0.0f));
+                                } else {
+                                    sKey[nn] = z;
+                                    if (ev.logit) ev.logit[nn] = z;
+                                }
+                            }
+                        }
+                        lds_barrier();
+                    }
+                }
+                // top K by key (largest first, lowest index on ties; NaN
+                // ranks last), one wave
+                if (wave == 0) {
+                    float key[kMaxActions / 64];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const float u0 = fmaf(kv[v], hq0, p0.w);
-                        const float u1 = fmaf(kv[v], hq1, p1.w);
+                    for (int i = 0; i < kMaxActions / 64; ++i) {
+                        const int a = lane + 64 * i;
+                        const float v = a < A ? sKey[a] : -INFINITY;
+                        key[i] = (v == v) ? v : -INFINITY;
+                    }
+                    unsigned taken = 0u;
+                    for (int r = 0; r < K; ++r) {
+                        float bv = -INFINITY;
+                        int bi = 0x7fffffff;
 #pragma unroll
-                        for (int c = 0; c < NC; ++c) {
-                            const float a0 = (c == ZC) ? u0 : fmaf(clf[c], p0.z, u0);
-                            const float a1 = (c == ZC) ? u1 : fmaf(clf[c], p1.z, u1);
-                            acc[c][v] = fminf(acc[c][v], fminf(a0, a1));
+                        for (int i = 0; i < kMaxActions / 64; ++i) {
+                            const int a = lane + 64 * i;
+                            if (a < A && !(taken >> i & 1u) && (key[i] > bv || bi == 0x7fffffff)) {
+                                bv = key[i];
+                                bi = a;
+                            }
+                        }
+#pragma unroll
+                        for (int off = 32; off > 0; off >>= 1) {
+                            const float ov = __shfl_xor(bv, off);
+                            const int oi = __shfl_xor(bi, off);
+                            if (oi != 0x7fffffff && (bi == 0x7fffffff || ov > bv || (ov == bv && oi < bi))) {
+                                bv = ov;
+                                bi = oi;
+                            }
+                        }
+                        if ((bi & 63) == lane) taken |= 1u << (bi >> 6);
+                        if (lane == 0) {
+                            sK[r] = bi;
+                            sInK[bi >> 5] |= 1u << (bi & 31);
+                            if (ev.topk) ev.topk[r] = bi;
+                        }
+                    }
+                }
+                lds_barrier();
+                // exact nearest distances of the K actions: the sweep's FP32
+                // expression over the same staged plans (min is exact, so
+                // the result does not depend on the order)
+                {
+                    float4 pe[PRE];
+#pragma unroll
+                    for (int i = 0; i < PRE; ++i) {
+                        const int j = tid + i * NT;
+                        pe[i] = j < n_vis ? tile[j] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                    }
+                    for (int r = 0; r < K; ++r) {
+                        const int a = sK[r];
+                        const int h = a / (NC * NV), c = (a / NV) % NC, v = a % NV;
+                        const float ch = (float)sCos[h], sh = (float)sSin[h];
+                        const float kvv = cfg.kv[v], clv = cfg.climb_f[c];
+                        float m = INFINITY;
+#pragma unroll
+                        for (int i = 0; i < PRE; ++i) {
+                            const float hq = fmaf(pe[i].x, ch, pe[i].y * sh);
+                            const float u = fmaf(kvv, hq, pe[i].w);
+                            const float d = (c == ZC) ? u : fmaf(clv, pe[i].z, u);
+                            m = fminf(m, d);
+                        }
+#pragma unroll
+                        for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
+                        if (lane == 0) sKm[wave][r] = m;
+                    }
+                }
+                for (int w = tid; w < kMaxActions / 32; w += NT) sBand[w] = 0u;
+                lds_barrier();
+                int band = 0;
+                if (wave == 0 && lane < K) {
+                    const int a = sK[lane];
+                    float m = INFINITY;
+                    for (int w = 0; w < NW; ++w) m = fminf(m, sKm[w][lane]);
+                    const double d2 = nearest_d2<NC, NV>(cfg, a, m);
+                    sD2[a] = d2;
+                    if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) {
+                        atomicOr(&sBand[a >> 5], 1u << (a & 31));
+                        band = 1;
+                    }
+                }
+                if (band) s_any = 1;
+                lds_barrier();
+                const int any_band = s_any;
+                lds_barrier();
+                if (tid == 0) s_any = 0;
+                if (any_band) band_recheck(s, n_row, rb);
+                // certificate: the best exact value among the K, less the tie
+                // band, must exceed every other action's goal term
+                if (wave == 0) {
+                    double v = -INFINITY;
+                    int a = 0x7fffffff;
+                    if (lane < K) {
+                        a = sK[lane];
+                        const int h = a / (NC * NV);
+                        v = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]).V;
+                    }
+                    const double vm = wave_max(v);
+                    const double thr = vm - cfg.tie_rel * fabs(vm);
+                    double tau = -INFINITY;
+                    for (int b = lane; b < A; b += 64)
+                        if (!(sInK[b >> 5] >> (b & 31) & 1u)) tau = fmax(tau, sG[b]);
+                    tau = wave_max(tau);
+                    const int ok = vm > -INFINITY && tau < thr;
+                    const int best = wave_min(lane < K && v >= thr ? a : 0x7fffffff);
+                    const int top1 = wave_min(lane < K && v == vm ? a : 0x7fffffff);
+                    const double vb = wave_max(lane < K && a == best ? v : -INFINITY);
+                    if (lane == 0) {
+                        st_cert = ok;
+                        st_best = best;
+                        st_top = vb < vm ? top1 : -1;
+                        pairs += (long long)(K + (prop.mode == FASTMDP_PROPOSE_MLP ? 1 : 0)) * n_vis;
+                        if (eval) {
+                            if (ev.cert) *ev.cert = ok;
+                            if (ev.pbest) *ev.pbest = ok ? best : -1;
+                        }
+                    }
+                }
+                lds_barrier();
+                cert = eval ? 0 : st_cert;                 // eval always runs the full sweep too
+                if (tid == 0 && !eval) {
+                    if (cert) ++hits;
+                    else ++misses;
+                }
+            } else if (prop.mode != FASTMDP_PROPOSE_NONE && tid == 0 && !eval) {
+                ++misses;                                  // row larger than one tile: full sweep
+            }
+        }
+
+        if (!cert) {
+            // 2-3. stage (compacted) and sweep the row chunk by chunk: every
+            //      lane, one heading's climb x speed actions over a slice of the
+            //      staged plans (two plans per round: v_min3)
+            float ch = 0.0f, sh = 0.0f;
+            float acc[NC][NV];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[c][v] = INFINITY;
+            for (int base = 0; base < n_row; base += tcap) {
+                int nv;
+                if (base == 0 && staged) {
+                    nv = n_vis;                            // staged by the proposal path
+                } else {
+                    if (base > 0) {
+                        lds_barrier();                     // previous chunk fully swept
+                        load_chunk(row, base);
+                    }
+                    nv = stage_chunk(s);
+                    if (base == 0 && single && !eval) {    // next row in flight during the sweep
+                        pre_n = n_next;
+                        if (pre_n > 0) load_chunk(row + 1, 0);
+                    }
+                    n_vis += nv;
+                    lds_barrier();
+                }
+                if (base == 0 && sweeper) {
+                    ch = (float)sCos[my_h];
+                    sh = (float)sSin[my_h];
+                }
+                const int npad = ((nv + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
+                if (sweeper) {
+                    for (int i = my_slice; i < npad; i += 2 * n_slices) {
+                        const float4 p0 = tile[i];
+                        const float4 p1 = tile[i + n_slices];
+                        const float hq0 = fmaf(p0.x, ch, p0.y * sh);
+                        const float hq1 = fmaf(p1.x, ch, p1.y * sh);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const float u0 = fmaf(kv[v], hq0, p0.w);
+                            const float u1 = fmaf(kv[v], hq1, p1.w);
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) {
+                                const float a0 = (c == ZC) ? u0 : fmaf(clf[c], p0.z, u0);
+                                const float a1 = (c == ZC) ? u1 : fmaf(clf[c], p1.z, u1);
+                                acc[c][v] = fminf(acc[c][v], fminf(a0, a1));
+                            }
                         }
                     }
                 }
             }
-        }
-        lds_barrier();                                   // tile is reused below
-        if (n_row == 0 && !eval) {
-            pre_n = n_next;
-            if (pre_n > 0) load_chunk(row + 1, 0);
-        }
+            lds_barrier();                                   // tile is reused below
+            if (n_row == 0 && !eval && !staged) {
+                pre_n = n_next;
+                if (pre_n > 0) load_chunk(row + 1, 0);
+            }
 
-        // slice partial minima, one row of A per slice
-        float *red = reinterpret_cast<float *>(tile);
-        if (sweeper) {
+            // slice partial minima, one row of A per slice
+            float *red = reinterpret_cast<float *>(tile);
+            if (sweeper) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
+                for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) red[my_slice * A + (my_h * NC + c) * NV + v] = acc[c][v];
-        }
-        for (int w = tid; w < kMaxActions / 32; w += NT) sBand[w] = 0u;
-        lds_barrier();
+                    for (int v = 0; v < NV; ++v) red[my_slice * A + (my_h * NC + c) * NV + v] = acc[c][v];
+            }
+            for (int w = tid; w < kMaxActions / 32; w += NT) sBand[w] = 0u;
+            lds_barrier();
 
-        // 4. per-action value, screened in FP32.  The nearest-plan squared
-        //    distance is m + |Delta|^2 with m from the FP32 sweep.  Each
-        //    action gets an FP32 bracket [lo, hi] of its value (1e-4 of the
-        //    terms it combines, far above the FP32 error); only actions whose
-        //    bracket reaches the largest lower bound can be chosen (or tie with
-        //    the choice) and are valued again in FP64 below.  Actions whose
-        //    nearest distance lands within kBand of the well radius get their
-        //    distance recomputed exactly in FP64 and are always valued in FP64,
-        //    so that well membership is decided in FP64.  The box and the
-        //    terrain clearance are decided in FP64.
-        const float gx32 = (float)(g[0] - s[0]), gy32 = (float)(g[1] - s[1]), gz32 = (float)(g[2] - s[2]);
-        int band = 0;
-        for (int a = tid; a < A; a += NT) {
-            float m = INFINITY;
-            for (int q = 0; q < n_part; ++q) m = fminf(m, red[q * A + a]);
-            const int h = a / (NC * NV);
-            const double dx = sCos[h], dy = sSin[h];
-            const double step = cfg.speed[a % NV] * cfg.dt;
-            const double dz = cfg.climb[(a / NV) % NC] * cfg.dt;
-            const double d2 = (double)m + step * step + dz * dz;
-            sD2[a] = d2;
-            const double ox = step * dx, oy = step * dy;
-            float lo = -INFINITY, hi = -INFINITY;
-            if (!outside_box(cfg, s[0] + ox, s[1] + oy, s[2] + dz)) {
-                const float ex = gx32 - (float)ox, ey = gy32 - (float)oy, ez = gz32 - (float)dz;
-                const float G = cfg.abs_r_goal_f *
-                                exp2f(cfg.log2_gamma_f * (sqrtf(ex * ex + ey * ey + ez * ez) * cfg.inv_ell_f));
-                const float d2f = (float)d2;
-                float pen = 0.0f;
-                if (d2f < cfg.R_intr2_f)
-                    pen = cfg.abs_r_intr_f * exp2f(cfg.log2_gamma_intr_f * (sqrtf(fmaxf(d2f, 0.0f)) * cfg.inv_ell_f));
-                if (tb.terr) {
-                    const double clr = s[2] + dz - terrain_height(tb, s[0] + ox, s[1] + oy);
-                    if (clr < cfg.R_terr)
-                        pen = fmaxf(pen, (float)(cfg.abs_r_terr * exp(cfg.log_gamma_terr * (fmax(clr, 0.0) / cfg.ell))));
-                }
-                const float V = G - pen;
-                const float e = 1e-4f * (G + pen) + 1e-30f;
-                lo = V - e;
-                hi = V + e;
-            }
-            if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) {
-                atomicOr(&sBand[a >> 5], 1u << (a & 31));
-                band = 1;
-                lo = -INFINITY;                            // valued in FP64 after the exact distance
-                hi = INFINITY;
-            }
-            sLo[a] = lo;
-            sHi[a] = hi;
-        }
-        if (band) s_any = 1;
-        lds_barrier();
-        const int any_band = s_any;
-        lds_barrier();
-        if (tid == 0) s_any = 0;                           // read by all before the reset
-        if (any_band) {                                    // uniform; almost never taken
-            for (int w = 0; w < (A + 31) / 32; ++w) {
-                unsigned bits = sBand[w];
-                while (bits) {
-                    const int a = w * 32 + __builtin_ctz(bits);
-                    bits &= bits - 1;
-                    const int h = a / (NC * NV);
-                    const double step = cfg.speed[a % NV] * cfg.dt;
-                    const double qx = s[0] + step * sCos[h], qy = s[1] + step * sSin[h];
-                    const double qz = s[2] + cfg.climb[(a / NV) % NC] * cfg.dt;
-                    double dmin = INFINITY;
-                    for (int j = tid; j < n_row; j += NT)
-                        if (entry_visible(tb, rb + j, seq))
-                            dmin = fmin(dmin, entry_d2(qx, qy, qz, tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]));
-                    dmin = -wave_max(-dmin);
-                    if (lane == 0) red_d[wave] = dmin;
-                    lds_barrier();
-                    if (tid == 0) {
-                        double d2 = red_d[0];
-                        for (int q = 1; q < NW; ++q) d2 = fmin(d2, red_d[q]);
-                        sD2[a] = d2;
-                    }
-                    lds_barrier();
-                }
-            }
-        }
-        if (eval) {
+            // 4. per-action value, screened in FP32.  The nearest-plan squared
+            //    distance is m + |Delta|^2 with m from the FP32 sweep.  Each
+            //    action gets an FP32 bracket [lo, hi] of its value (1e-4 of the
+            //    terms it combines, far above the FP32 error); only actions whose
+            //    bracket reaches the largest lower bound can be chosen (or tie with
+            //    the choice) and are valued again in FP64 below.  Actions whose
+            //    nearest distance lands within kBand of the well radius get their
+            //    distance recomputed exactly in FP64 and are always valued in FP64,
+            //    so that well membership is decided in FP64.  The box and the
+            //    terrain clearance are decided in FP64.
+            const float gx32 = (float)(g[0] - s[0]), gy32 = (float)(g[1] - s[1]), gz32 = (float)(g[2] - s[2]);
+            int band = 0;
             for (int a = tid; a < A; a += NT) {
+                float m = INFINITY;
+                for (int q = 0; q < n_part; ++q) m = fminf(m, red[q * A + a]);
                 const int h = a / (NC * NV);
-                const Scored r = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]);
-                if (ev.V) ev.V[a] = r.V;
-                if (ev.G) ev.G[a] = r.G;
-                if (ev.I) ev.I[a] = r.I;
-                if (ev.T) ev.T[a] = r.T;
+                const double dx = sCos[h], dy = sSin[h];
+                const double step = cfg.speed[a % NV] * cfg.dt;
+                const double dz = cfg.climb[(a / NV) % NC] * cfg.dt;
+                const double d2 = nearest_d2<NC, NV>(cfg, a, m);
+                sD2[a] = d2;
+                const double ox = step * dx, oy = step * dy;
+                float lo = -INFINITY, hi = -INFINITY;
+                if (!outside_box(cfg, s[0] + ox, s[1] + oy, s[2] + dz)) {
+                    const float ex = gx32 - (float)ox, ey = gy32 - (float)oy, ez = gz32 - (float)dz;
+                    const float G = cfg.abs_r_goal_f *
+                                    exp2f(cfg.log2_gamma_f * (sqrtf(ex * ex + ey * ey + ez * ez) * cfg.inv_ell_f));
+                    const float d2f = (float)d2;
+                    float pen = 0.0f;
+                    if (d2f < cfg.R_intr2_f)
+                        pen = cfg.abs_r_intr_f * exp2f(cfg.log2_gamma_intr_f * (sqrtf(fmaxf(d2f, 0.0f)) * cfg.inv_ell_f));
+                    if (tb.terr) {
+                        const double clr = s[2] + dz - terrain_height(tb, s[0] + ox, s[1] + oy);
+                        if (clr < cfg.R_terr)
+                            pen = fmaxf(pen, (float)(cfg.abs_r_terr * exp(cfg.log_gamma_terr * (fmax(clr, 0.0) / cfg.ell))));
+                    }
+                    const float V = G - pen;
+                    const float e = 1e-4f * (G + pen) + 1e-30f;
+                    lo = V - e;
+                    hi = V + e;
+                }
+                if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) {
+                    atomicOr(&sBand[a >> 5], 1u << (a & 31));
+                    band = 1;
+                    lo = -INFINITY;                            // valued in FP64 after the exact distance
+                    hi = INFINITY;
+                }
+                sLo[a] = lo;
+                sHi[a] = hi;
             }
-        } else if (!single) {
-            pre_n = n_next;                                // in flight during the argmax and advance
-            if (pre_n > 0) load_chunk(row + 1, 0);
+            if (band) s_any = 1;
+            lds_barrier();
+            const int any_band = s_any;
+            lds_barrier();
+            if (tid == 0) s_any = 0;                           // read by all before the reset
+            if (any_band) band_recheck(s, n_row, rb);          // uniform; almost never taken
+            if (eval) {
+                for (int a = tid; a < A; a += NT) {
+                    const int h = a / (NC * NV);
+                    const Scored r = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]);
+                    if (ev.V) ev.V[a] = r.V;
+                    if (ev.G) ev.G[a] = r.G;
+                    if (ev.I) ev.I[a] = r.I;
+                    if (ev.T) ev.T[a] = r.T;
+                }
+            } else if (!single) {
+                pre_n = n_next;                                // in flight during the argmax and advance
+                if (pre_n > 0) load_chunk(row + 1, 0);
+            }
+
+            // 5. argmax (one wave: largest value, then the lowest index inside
+            //    the tie band)
+            if (wave == 0) {
+                float lb = -INFINITY;
+                for (int a = lane; a < A; a += 64) lb = fmaxf(lb, sLo[a]);
+                lb = wave_maxf(lb);
+                const float cut = lb - 1e-6f * fabsf(lb);
+                double vm = -INFINITY;
+                for (int a = lane; a < A; a += 64) {
+                    double v = -INFINITY;
+                    if (eval || sHi[a] >= cut) {
+                        const int h = a / (NC * NV);
+                        v = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]).V;
+                    }
+                    sV[a] = v;
+                    vm = fmax(vm, v);
+                }
+                vm = wave_max(vm);
+                const double thr = vm - cfg.tie_rel * fabs(vm);
+                int li = 0x7fffffff;
+                for (int a = lane; a < A; a += 64)
+                    if (sV[a] >= thr) { li = a; break; }
+                li = wave_min(li);
+                const int best = vm == -INFINITY ? -1 : li;
+                // inside the tie band the chosen action may not be the largest:
+                // remember the (lowest-index) largest for the acceptance check
+                int top = -1;
+                if (best >= 0 && sV[best] < vm) {
+                    int ti = 0x7fffffff;
+                    for (int a = lane; a < A; a += 64)
+                        if (sV[a] == vm) { ti = a; break; }
+                    top = wave_min(ti);
+                }
+                if (lane == 0) {
+                    st_best = best;
+                    st_top = top;
+                    pairs += (long long)A * n_vis;             // pairs with the plans this request sees
+                    if (eval && ev.best) *ev.best = best;
+                }
+            }
         }
 
-        // 5-6. argmax (one wave: largest value, then the lowest index inside
-        //      the tie band) and advance
-        if (wave == 0) {
-            float lb = -INFINITY;
-            for (int a = lane; a < A; a += 64) lb = fmaxf(lb, sLo[a]);
-            lb = wave_maxf(lb);
-            const float cut = lb - 1e-6f * fabsf(lb);
-            double vm = -INFINITY;
-            for (int a = lane; a < A; a += 64) {
-                double v = -INFINITY;
-                if (eval || sHi[a] >= cut) {
-                    const int h = a / (NC * NV);
-                    v = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]).V;
-                }
-                sV[a] = v;
-                vm = fmax(vm, v);
-            }
-            vm = wave_max(vm);
-            const double thr = vm - cfg.tie_rel * fabs(vm);
-            int li = 0x7fffffff;
-            for (int a = lane; a < A; a += 64)
-                if (sV[a] >= thr) { li = a; break; }
-            li = wave_min(li);
-            const int best = vm == -INFINITY ? -1 : li;
-            // inside the tie band the chosen action may not be the largest:
-            // remember the (lowest-index) largest for the acceptance check
-            int top = -1;
-            if (best >= 0 && sV[best] < vm) {
-                int ti = 0x7fffffff;
-                for (int a = lane; a < A; a += 64)
-                    if (sV[a] == vm) { ti = a; break; }
-                top = wave_min(ti);
-            }
-            if (lane == 0) {
-                pairs += (long long)A * n_vis;             // pairs with the plans this request sees
-                if (eval) {
-                    if (ev.best) *ev.best = best;
-                } else if (best < 0) {
-                    st_status = FASTMDP_NO_VALID_ACTION;
-                } else {
-                    const int h = best / (NC * NV);
-                    const Scored r = score_action(cfg, tb, best, s, g, sCos[h], sSin[h], sD2[best]);
-                    const size_t p = pt_base + n;
-                    tr.xyz[p * 3 + 0] = r.x;
-                    tr.xyz[p * 3 + 1] = r.y;
-                    tr.xyz[p * 3 + 2] = r.z;
-                    tr.act[p] = best;
-                    tr.val[p] = r.V;
-                    tr.seen[p] = n_row;
-                    tr.ep[p] = epoch;
-                    tr.top[p] = top;
-                    tr.col[p] = -1;
-                    st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
-                    st_n = n + 1;
-                    if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
-                    else if (r.clr < 0.0) st_status = FASTMDP_REJECT_TERRAIN;
-                }
+        // 6. advance (thread 0, which also wrote st_best and st_top)
+        if (tid == 0 && !eval) {
+            const int best = st_best, top = st_top;
+            if (best < 0) {
+                st_status = FASTMDP_NO_VALID_ACTION;
+            } else {
+                const int h = best / (NC * NV);
+                const Scored r = score_action(cfg, tb, best, s, g, sCos[h], sSin[h], sD2[best]);
+                const size_t p = pt_base + n;
+                tr.xyz[p * 3 + 0] = r.x;
+                tr.xyz[p * 3 + 1] = r.y;
+                tr.xyz[p * 3 + 2] = r.z;
+                tr.act[p] = best;
+                tr.val[p] = r.V;
+                tr.seen[p] = n_row;
+                tr.ep[p] = epoch;
+                tr.top[p] = top;
+                tr.col[p] = -1;
+                st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
+                st_n = n + 1;
+                if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
+                else if (r.clr < 0.0) st_status = FASTMDP_REJECT_TERRAIN;
             }
         }
         steps_here += 1;
@@ -571,6 +825,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     if (tid == 0) {
         S.pairs += pairs;
         S.steps += steps_here;
+        S.cert_hit += hits;
+        S.cert_miss += misses;
     }
 }
 
@@ -579,19 +835,28 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
 // ---------------------------------------------------------------------------
 template <int NC, int NV, int ZC>
 static hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
-                           const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev) {
+                           const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
+                           const PropArgs &prop) {
     (void)nt;
-    hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC>), dim3(nblk), dim3(kPlanThreads), 0, st, c, t, s, list,
-                       tr, budget, validate, epoch, ev);
+    if (prop.mode == FASTMDP_PROPOSE_NONE)
+        hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
+                           t, s, list, tr, budget, validate, epoch, ev, prop);
+    else
+        hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, true>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
+                           t, s, list, tr, budget, validate, epoch, ev, prop);
     return hipGetLastError();
 }
 
 #define FMDP_SHAPE(NC, NV, ZC) \
-    if (c.n_climb == NC && c.n_speed == NV && zc == ZC) return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, ev);
+    if (c.n_climb == NC && c.n_speed == NV && zc == ZC) \
+        return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, ev, prop);
 
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
-                          const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev) {
+                          const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
+                          const PropArgs &prop) {
     const int zc = c.zero_climb;
+    if (prop.mode != FASTMDP_PROPOSE_NONE && (prop.k < 1 || prop.k > FASTMDP_MAX_TOPK || prop.k > c.n_actions))
+        return hipErrorInvalidValue;
     FMDP_SHAPE(1, 1, 0) FMDP_SHAPE(1, 1, -1) FMDP_SHAPE(1, 2, 0) FMDP_SHAPE(1, 2, -1)
     FMDP_SHAPE(1, 3, 0) FMDP_SHAPE(1, 3, -1)
     FMDP_SHAPE(2, 1, -1) FMDP_SHAPE(2, 2, -1) FMDP_SHAPE(2, 3, -1)

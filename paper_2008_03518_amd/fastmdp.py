@@ -16,6 +16,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libfastmdp.so")
 MAX_ACT_DIM = 8
 TIE_REL = 1e-9
+N_FEAT = 96
+MLP_HIDDEN = 256
+MAX_TOPK = 16
+PROPOSE_NONE, PROPOSE_MLP, PROPOSE_GOAL = 0, 1, 2
 
 E_INVAL, E_CAPACITY, E_DEVICE, E_CONFLICT, E_NOMEM, E_IO = -1, -2, -3, -4, -5, -6
 OK, REJECT_SEPARATION, REJECT_TERRAIN, REJECT_ORIGIN, TIMEOUT, NO_VALID_ACTION = 0, 1, 2, 3, 4, 5
@@ -85,6 +89,27 @@ def _load_lib():
     lib.fastmdp_load_table.argtypes = [P, C.c_char_p]
     lib.fastmdp_strerror.argtypes = [C.c_int]
     lib.fastmdp_strerror.restype = C.c_char_p
+    # learned action proposal
+    lib.fastmdp_mlp_create.argtypes = [I32, I32, I32, I32, C.POINTER(P)]
+    lib.fastmdp_mlp_destroy.argtypes = [P]
+    lib.fastmdp_mlp_destroy.restype = None
+    lib.fastmdp_mlp_num_params.argtypes = [P]
+    lib.fastmdp_mlp_num_params.restype = I64
+    lib.fastmdp_mlp_set_params.argtypes = [P, fp]
+    lib.fastmdp_mlp_get_params.argtypes = [P, fp]
+    lib.fastmdp_mlp_forward.argtypes = [P, I32, P, P]
+    lib.fastmdp_mlp_gradient.argtypes = [P, I32, P, P, fp, fp]
+    lib.fastmdp_mlp_train_step.argtypes = [P, I32, P, P, C.c_float, fp]
+    lib.fastmdp_features.argtypes = [P, I32, P, P, P, P, P]
+    lib.fastmdp_next_seq.argtypes = [P]
+    lib.fastmdp_set_proposal.argtypes = [P, I32, I32, P]
+    lib.fastmdp_eval_proposal.argtypes = [P, C.POINTER(_State), fp, fp, ip, ip, ip]
+    lib.fastmdp_proposal_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64)]
+    lib.fastmdp_device_alloc.argtypes = [I64, C.POINTER(P)]
+    lib.fastmdp_device_free.argtypes = [P]
+    lib.fastmdp_copy_to_device.argtypes = [P, P, I64]
+    lib.fastmdp_copy_to_host.argtypes = [P, P, I64]
+    lib.fastmdp_gather_rows.argtypes = [P, P, I64, P, I64, I32]
     return lib
 
 
@@ -95,6 +120,11 @@ EXPORTS = [
     "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_commit_plan", "fastmdp_num_plans", "fastmdp_plan_fcfs",
     "fastmdp_last_stats", "fastmdp_save_table", "fastmdp_load_table", "fastmdp_strerror",
     "fastmdp_table_snapshot", "fastmdp_table_rewind",
+    "fastmdp_mlp_create", "fastmdp_mlp_destroy", "fastmdp_mlp_num_params", "fastmdp_mlp_set_params",
+    "fastmdp_mlp_get_params", "fastmdp_mlp_forward", "fastmdp_mlp_gradient", "fastmdp_mlp_train_step",
+    "fastmdp_features", "fastmdp_next_seq", "fastmdp_set_proposal", "fastmdp_eval_proposal",
+    "fastmdp_proposal_stats", "fastmdp_device_alloc", "fastmdp_device_free", "fastmdp_copy_to_device",
+    "fastmdp_copy_to_host", "fastmdp_gather_rows",
 ]
 
 
@@ -118,6 +148,88 @@ def _iptr(a):
 
 def _fptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class DeviceArray:
+    """A C-contiguous array in device memory owned by this object (allocated
+    through the library, so no second HIP runtime enters the process)."""
+
+    def __init__(self, shape, dtype):
+        self.shape = tuple(int(d) for d in np.atleast_1d(shape)) if not isinstance(shape, tuple) else shape
+        self.dtype = np.dtype(dtype)
+        self.nbytes = int(np.prod(self.shape)) * self.dtype.itemsize
+        self._p = C.c_void_p()
+        if self.nbytes > 0:
+            _check("fastmdp_device_alloc", _lib.fastmdp_device_alloc(self.nbytes, C.byref(self._p)))
+
+    @classmethod
+    def from_host(cls, a, dtype=None) -> "DeviceArray":
+        a = np.ascontiguousarray(a, dtype=dtype)
+        d = cls(a.shape, a.dtype)
+        if d.nbytes:
+            _check("fastmdp_copy_to_device", _lib.fastmdp_copy_to_device(d._p, a.ctypes.data_as(C.c_void_p),
+                                                                         d.nbytes))
+        return d
+
+    @property
+    def ptr(self) -> int:
+        view = getattr(self, "_view", None)
+        return view[1] if view else int(self._p.value or 0)
+
+    def __len__(self) -> int:
+        return self.shape[0]
+
+    def row_ptr(self, i: int) -> int:
+        return self.ptr + int(i) * (self.nbytes // max(self.shape[0], 1))
+
+    def numpy(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=self.dtype)
+        if self.nbytes:
+            _check("fastmdp_copy_to_host", _lib.fastmdp_copy_to_host(out.ctypes.data_as(C.c_void_p),
+                                                                     C.c_void_p(self.ptr), self.nbytes))
+        return out
+
+    def rows(self, i: int, k: int) -> "DeviceArray":
+        """Rows [i, i + k) as a view (no copy; keeps this array alive)."""
+        if not (0 <= i and k >= 0 and i + k <= self.shape[0]):
+            raise IndexError((i, k, self.shape))
+        v = DeviceArray.__new__(DeviceArray)
+        v.shape = (int(k),) + self.shape[1:]
+        v.dtype = self.dtype
+        v.nbytes = int(k) * (self.nbytes // max(self.shape[0], 1))
+        v._p = C.c_void_p()
+        v._view = (self, self.row_ptr(i))
+        return v
+
+    def gather(self, idx) -> "DeviceArray":
+        """Rows idx (host or device int64) as a new array."""
+        di = idx if isinstance(idx, DeviceArray) else DeviceArray.from_host(np.asarray(idx, dtype=np.int64))
+        out = DeviceArray((len(di),) + self.shape[1:], self.dtype)
+        row = self.nbytes // max(self.shape[0], 1)
+        if len(di):
+            _check("fastmdp_gather_rows", _lib.fastmdp_gather_rows(out._p, C.c_void_p(self.ptr), self.shape[0],
+                                                                   C.c_void_p(di.ptr), len(di), row))
+        return out
+
+    def free(self):
+        if getattr(self, "_p", None) and self._p.value:
+            _lib.fastmdp_device_free(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _dev(a, dtype) -> DeviceArray:
+    """A device array of the given numpy dtype (uploaded unless it already is one)."""
+    if isinstance(a, DeviceArray):
+        if a.dtype != np.dtype(dtype):
+            raise TypeError(f"device array of {a.dtype}, expected {np.dtype(dtype)}")
+        return a
+    return DeviceArray.from_host(np.asarray(a), dtype=dtype)
 
 
 def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_launch: int = 0,
@@ -305,11 +417,126 @@ class Context:
         _check("fastmdp_last_stats", _lib.fastmdp_last_stats(self._h, *[C.byref(x) for x in v], C.byref(ms)))
         return dict(pairs=v[0].value, steps=v[1].value, resumes=v[2].value, launches=v[3].value, kernel_ms=ms.value)
 
+    # -- learned action proposal ------------------------------------------
+    def next_seq(self) -> int:
+        return _check("fastmdp_next_seq", _lib.fastmdp_next_seq(self._h))
+
+    def features(self, states, goals, rows, seqs) -> DeviceArray:
+        """Proposal features [n, 96] (device array) of FP64 states/goals [n, 3]
+        against the plans of rows[i] + 1 visible to sequence number seqs[i]."""
+        st, gl = _dev(states, np.float64), _dev(goals, np.float64)
+        rw, sq = _dev(rows, np.int32), _dev(seqs, np.int32)
+        n = int(st.shape[0])
+        out = DeviceArray((n, N_FEAT), np.float32)
+        _check("fastmdp_features", _lib.fastmdp_features(self._h, n, st.ptr, gl.ptr, rw.ptr, sq.ptr, out.ptr))
+        return out
+
+    def set_proposal(self, mode: int, top_k: int = 8, net: "Optional[Mlp]" = None) -> None:
+        _check("fastmdp_set_proposal", _lib.fastmdp_set_proposal(self._h, int(mode), int(top_k),
+                                                                 net._h if net is not None else None))
+        self._net = net if mode == PROPOSE_MLP else None      # keep the network alive while selected
+        self._top_k = int(top_k)
+
+    def eval_proposal(self, s, g, t: int) -> dict:
+        st = _State(_Vec3(*[float(v) for v in s]), _Vec3(*[float(v) for v in g]), int(t))
+        f = np.zeros(N_FEAT, dtype=np.float32)
+        lg = np.zeros(self.A, dtype=np.float32)
+        tk = np.zeros(MAX_TOPK, dtype=np.int32)
+        ce = np.zeros(1, dtype=np.int32)
+        b = np.zeros(1, dtype=np.int32)
+        _check("fastmdp_eval_proposal", _lib.fastmdp_eval_proposal(self._h, C.byref(st), _fptr(f), _fptr(lg), _iptr(tk),
+                                                                   _iptr(ce), _iptr(b)))
+        return dict(features=f, logits=lg, topk=tk[: self._top_k].copy(), certified=bool(ce[0]), best=int(b[0]))
+
+    def proposal_stats(self) -> dict:
+        a, b = C.c_int64(), C.c_int64()
+        _check("fastmdp_proposal_stats", _lib.fastmdp_proposal_stats(self._h, C.byref(a), C.byref(b)))
+        return dict(certified=a.value, fallbacks=b.value)
+
     def save_table(self, path: str) -> None:
         _check("fastmdp_save_table", _lib.fastmdp_save_table(self._h, path.encode()))
 
     def load_table(self, path: str) -> None:
         _check("fastmdp_load_table", _lib.fastmdp_load_table(self._h, path.encode()))
+
+
+def pack_params(params: dict) -> np.ndarray:
+    """Packed FP32 parameter vector of the library from weights in the
+    x @ W convention (W1 [in, hid], W2 [hid, hid], W3 [hid, out], biases)."""
+    parts = [params["W1"].T, params["b1"], params["W2"].T, params["b2"], params["W3"].T, params["b3"]]
+    return np.concatenate([np.ascontiguousarray(p, dtype=np.float32).ravel() for p in parts])
+
+
+def unpack_params(v: np.ndarray, n_in: int, n_hid: int, n_out: int) -> dict:
+    """Inverse of pack_params (float64 arrays in the x @ W convention)."""
+    v = np.asarray(v, dtype=np.float64)
+    out, o = {}, 0
+    for name, shape in (("W1", (n_hid, n_in)), ("b1", (n_hid,)), ("W2", (n_hid, n_hid)), ("b2", (n_hid,)),
+                        ("W3", (n_out, n_hid)), ("b3", (n_out,))):
+        k = int(np.prod(shape))
+        a = v[o: o + k].reshape(shape)
+        out[name] = a.T.copy() if name.startswith("W") else a.copy()
+        o += k
+    return out
+
+
+class Mlp:
+    """The proposal network on the current HIP device (BF16 MFMA kernels,
+    FP32 master weights, Adam)."""
+
+    def __init__(self, n_out: int, n_in: int = N_FEAT, n_hidden: int = MLP_HIDDEN, max_batch: int = 4096):
+        self.n_in, self.n_hid, self.n_out, self.max_batch = int(n_in), int(n_hidden), int(n_out), int(max_batch)
+        h = C.c_void_p()
+        _check("fastmdp_mlp_create", _lib.fastmdp_mlp_create(self.n_in, self.n_hid, self.n_out, self.max_batch,
+                                                             C.byref(h)))
+        self._h = h
+        self.n_params = int(_lib.fastmdp_mlp_num_params(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fastmdp_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: dict) -> None:
+        v = pack_params(params)
+        assert v.size == self.n_params
+        _check("fastmdp_mlp_set_params", _lib.fastmdp_mlp_set_params(self._h, _fptr(v)))
+
+    def get_params(self) -> dict:
+        v = np.zeros(self.n_params, dtype=np.float32)
+        _check("fastmdp_mlp_get_params", _lib.fastmdp_mlp_get_params(self._h, _fptr(v)))
+        return unpack_params(v, self.n_in, self.n_hid, self.n_out)
+
+    def forward(self, x) -> np.ndarray:
+        """Logits [B, n_out] (host) of features x [B, n_in] (host or device)."""
+        xd = _dev(x, np.float32)
+        out = DeviceArray((xd.shape[0], self.n_out), np.float32)
+        _check("fastmdp_mlp_forward", _lib.fastmdp_mlp_forward(self._h, int(xd.shape[0]), xd.ptr, out.ptr))
+        return out.numpy()
+
+    def gradient(self, x, y):
+        """(gradients in the x @ W convention, mean loss) of a batch."""
+        xd, yd = _dev(x, np.float32), _dev(y, np.int32)
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        _check("fastmdp_mlp_gradient", _lib.fastmdp_mlp_gradient(self._h, int(xd.shape[0]), xd.ptr, yd.ptr,
+                                                                 _fptr(g), _fptr(loss)))
+        return unpack_params(g, self.n_in, self.n_hid, self.n_out), float(loss[0])
+
+    def train_step(self, x, y, lr: float) -> float:
+        """One Adam step on the batch (host or device arrays); returns its loss
+        before the step."""
+        xd, yd = _dev(x, np.float32), _dev(y, np.int32)
+        loss = np.zeros(1, dtype=np.float32)
+        _check("fastmdp_mlp_train_step", _lib.fastmdp_mlp_train_step(self._h, int(xd.shape[0]), xd.ptr, yd.ptr,
+                                                                     float(lr), _fptr(loss)))
+        return float(loss[0])
 
 
 def context_for(scenario, max_slots: int = 1, steps_per_launch: int = 0, planner_threads: int = 0) -> Context:

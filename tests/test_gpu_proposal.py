@@ -1,0 +1,331 @@
+"""Learned action proposal on the GPU, through the C ABI.
+
+* the network's BF16 MFMA kernels against the FP64 oracle: logits,
+  gradients (per-tensor relative L2 <= 2e-2, cosine >= 0.999) and the Adam
+  step;
+* the features against the oracle's definition (batch kernel), and the
+  planner's in-loop features, logits and top-k against the batch kernels;
+* the proposal path's plans against the full sweep, bit for bit, with
+  untrained, trained and no-network (goal-term) rankings;
+* what training gains: accuracy and certified steps, trained vs untrained.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+from oracle import mlp as OM  # noqa: E402
+from oracle import proposal as OP  # noqa: E402
+from paper_2008_03518_amd import scenario as S  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 2e-2
+COSINE = 0.999
+
+
+@pytest.fixture(scope="module")
+def fm():
+    from paper_2008_03518_amd import fastmdp
+    return fastmdp
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _bf16(a):
+    """Round to the nearest BF16 (even on ties), as float64: the parameters and
+    inputs the kernels actually multiply."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _rounded(params):
+    return {k: (_bf16(v) if k.startswith("W") else np.asarray(v, dtype=np.float32).astype(np.float64))
+            for k, v in params.items()}
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _cos(a, b):
+    a, b = a.ravel(), b.ravel()
+    return float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+
+
+def _params(n_out, seed, hidden=256):
+    rng = np.random.default_rng(seed)
+    p = OM.init_params(rng, n_out, hidden=hidden)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0.0, 0.05, p[k].shape)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# network kernels
+# ---------------------------------------------------------------------------
+def test_mlp_forward_matches_oracle(fm):
+    rng = np.random.default_rng(3)
+    for n_out, batch in ((360, 96), (81, 37), (1, 5)):
+        params = _params(n_out, 10 + n_out)
+        X = rng.uniform(0.0, 1.0, (batch, OM.N_FEAT))
+        net = fm.Mlp(n_out, max_batch=128)
+        net.set_params(params)
+        got = net.forward(X.astype(np.float32)).astype(np.float64)
+        ref, _ = OM.forward(_rounded(params), _bf16(X))
+        r = _rel_l2(got, ref)
+        _log(f"[mlp forward] n_out {n_out} batch {batch}: rel-L2 {r:.2e}")
+        assert r <= 1e-2
+        assert np.max(np.abs(got - ref)) <= 3e-2 * np.max(np.abs(ref))
+        net.close()
+
+
+def test_mlp_gradient_matches_oracle(fm):
+    rng = np.random.default_rng(4)
+    for n_out, batch in ((360, 256), (81, 64)):
+        params = _params(n_out, 20 + n_out)
+        X = rng.uniform(0.0, 1.0, (batch, OM.N_FEAT))
+        y = rng.integers(0, n_out, batch)
+        net = fm.Mlp(n_out, max_batch=batch)
+        net.set_params(params)
+        g, loss = net.gradient(X.astype(np.float32), y.astype(np.int32))
+        P = _rounded(params)
+        Xr = _bf16(X)
+        ref = OM.backward(P, Xr, y)
+        ref_loss = OM.loss(P, Xr, y)
+        assert abs(loss - ref_loss) <= 1e-2 * ref_loss
+        for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            r, c = _rel_l2(g[k], ref[k]), _cos(g[k], ref[k])
+            _log(f"[mlp grad] n_out {n_out} {k}: rel-L2 {r:.2e} cosine {c:.6f}")
+            assert r <= REL_L2 and c >= COSINE, k
+        net.close()
+
+
+def test_mlp_adam_step_matches_oracle(fm):
+    rng = np.random.default_rng(5)
+    n_out, batch, lr = 360, 128, 1e-3
+    params = _params(n_out, 30)
+    X = rng.uniform(0.0, 1.0, (batch, OM.N_FEAT))
+    y = rng.integers(0, n_out, batch)
+    net = fm.Mlp(n_out, max_batch=batch)
+    net.set_params(params)
+    p0 = net.get_params()
+    net.train_step(X.astype(np.float32), y.astype(np.int32), lr)
+    p1 = net.get_params()
+    ref_g = OM.backward(_rounded(params), _bf16(X), y)
+    for k in p0:
+        g = ref_g[k]
+        want, _, _ = OP.adam_step(p0[k], g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+        # the first step moves every parameter by lr * g / (|g| + eps): compare
+        # where the FP64 gradient is clearly non-zero; a BF16 gradient may still
+        # flip the sign of a small component (bounded by the gradient test), so
+        # allow one such element in a thousand
+        sure = np.abs(g) > 1e-2 * np.max(np.abs(g))
+        d = np.abs((p1[k] - p0[k])[sure] - (want - p0[k])[sure])
+        bad = int(np.sum(d > 1e-3 * lr + 1e-7))
+        _log(f"[adam] {k}: {int(sure.sum())} checked, {bad} sign flips, median |diff| "
+             f"{np.median(d) if d.size else 0:.2e}")
+        assert d.size and bad <= max(1, d.size // 1000)
+        assert np.all(np.abs(p1[k] - p0[k]) <= lr * (1 + 1e-3) + 1e-7)
+    # a fixed batch: the loss falls
+    losses = [net.train_step(X.astype(np.float32), y.astype(np.int32), lr) for _ in range(30)]
+    assert losses[-1] < 0.7 * losses[0]
+    net.close()
+
+
+# ---------------------------------------------------------------------------
+# features
+# ---------------------------------------------------------------------------
+def _row_positions(sc, row):
+    off = sc.plans.offsets()
+    j = np.flatnonzero((sc.plans.t0 <= row) & (row < sc.plans.t0 + sc.plans.length))
+    return sc.plans.xyz[off[j] + (row - sc.plans.t0[j])].astype(np.float64)
+
+
+def _ambiguous(s, g, P):
+    """Feature indices an FP32 evaluation may legitimately assign differently:
+    plans within 1e-3 m of the 600 m radius, 1e-4 rad of a sector edge, or
+    1e-3 m of the horizontal plane through s."""
+    bad = set()
+    bx, by = g[0] - s[0], g[1] - s[1]
+    rh = math.hypot(bx, by)
+    ux, uy = (bx / rh, by / rh) if rh > 0 else (1.0, 0.0)
+    for p in P:
+        q = p - s
+        d = float(np.linalg.norm(q))
+        if d >= OM.R_FEAT + 1e-3:
+            continue
+        if abs(d - OM.R_FEAT) < 1e-3:
+            bad.update(range(0, 64))
+            bad.update((74, 75))
+        phi = math.atan2(-q[0] * uy + q[1] * ux, q[0] * ux + q[1] * uy)
+        x = (phi + math.pi) * OM.SECTORS / (2 * math.pi)
+        ks = {min(OM.SECTORS - 1, int(math.floor(x)))}
+        tol_rad = 1e-3 + 1e-3 / max(d, 1e-3)
+        if abs(x - round(x)) < tol_rad * OM.SECTORS / (2 * math.pi):
+            ks |= {int(round(x)) % OM.SECTORS, (int(round(x)) - 1) % OM.SECTORS}
+        us = {0 if q[2] >= 0 else 1}
+        if abs(q[2]) < 1e-3:
+            us = {0, 1}
+        if len(ks) > 1 or len(us) > 1:
+            for k in ks:
+                for u in us:
+                    bad.update((2 * k + u, 32 + 2 * k + u))
+    return bad
+
+
+def _states(sc, n, seed):
+    rng = np.random.default_rng(seed)
+    off = sc.plans.offsets()
+    lo, hi = np.array(sc.cfg.box_min), np.array(sc.cfg.box_max)
+    out = []
+    while len(out) < n:
+        j = int(rng.integers(sc.plans.n))
+        L = int(sc.plans.length[j])
+        if L < 3:
+            continue
+        k = int(rng.integers(0, L - 1))
+        p = sc.plans.xyz[off[j] + k + 1].astype(np.float64)
+        s = np.clip(p + rng.uniform(-400, 400, 3) * np.array([1.0, 1.0, 0.5]), lo + 1.0, hi - 1.0)
+        g = np.array([rng.uniform(lo[0], hi[0]), rng.uniform(lo[1], hi[1]), rng.uniform(100, 900)])
+        out.append((s, g, int(sc.plans.t0[j]) + k))
+    return out
+
+
+def test_features_match_oracle(fm):
+    sc = S.large_actions(seed=5, n_plans=3000, n_requests=1)
+    cases = _states(sc, 200, 6)
+    with fm.context_for(sc) as ctx:
+        seq = ctx.next_seq()
+        st = np.array([c[0] for c in cases])
+        gl = np.array([c[1] for c in cases])
+        rw = np.array([c[2] for c in cases], dtype=np.int32)
+        F = ctx.features(st, gl, rw, np.full(len(cases), seq, dtype=np.int32)).numpy().astype(np.float64)
+    n_traffic = skipped = 0
+    for i, (s, g, t) in enumerate(cases):
+        P = _row_positions(sc, t + 1)
+        ref = OM.features(s, g, P, sc.cfg)
+        bad = _ambiguous(s, g, P)
+        skipped += len(bad)
+        for f in range(OM.N_FEAT):
+            if f in bad:
+                continue
+            tol = 1e-5 * max(1.0, abs(ref[f]))
+            assert abs(F[i, f] - ref[f]) <= tol, (i, f, F[i, f], ref[f])
+        n_traffic += int(ref[74] > 0)
+    _log(f"[features] {len(cases)} states, {n_traffic} with plans within 600 m, {skipped} ambiguous entries skipped")
+    assert n_traffic > 100
+
+
+def test_planner_in_loop_proposal_matches_batch_kernels(fm):
+    sc = S.large_actions(seed=7, n_plans=3000, n_requests=1)
+    A = sc.cfg.n_actions
+    net = fm.Mlp(A)
+    net.set_params(_params(A, 40))
+    cases = _states(sc, 40, 8)
+    n_cert = 0
+    with fm.context_for(sc) as ctx:
+        seq = ctx.next_seq()
+        for mode in (fm.PROPOSE_MLP, fm.PROPOSE_GOAL):
+            ctx.set_proposal(mode, 8, net if mode == fm.PROPOSE_MLP else None)
+            for s, g, t in cases:
+                pr = ctx.eval_proposal(s, g, t)
+                full = ctx.eval_step(s, g, t)
+                if mode == fm.PROPOSE_MLP:
+                    F = ctx.features(s[None], g[None], np.array([t], np.int32), np.array([seq], np.int32))
+                    assert np.array_equal(pr["features"], F.numpy()[0])
+                    lg = net.forward(F)[0]
+                    assert np.allclose(pr["logits"], lg, rtol=1e-5, atol=1e-5)
+                    keys = pr["logits"]
+                else:
+                    keys = np.where(np.isfinite(full["V"]), full["G"], -np.inf).astype(np.float32)
+                assert list(pr["topk"]) == OP.top_k(keys, 8)
+                if pr["certified"]:
+                    n_cert += 1
+                    assert pr["best"] == full["best"]
+                    ok, a = OP.certify(full["V"][pr["topk"]], pr["topk"],
+                                       np.where(np.isfinite(full["V"]), full["G"], -np.inf), 1e-9)
+                    assert ok and a == full["best"]
+    _log(f"[in-loop proposal] {n_cert} of {2 * len(cases)} states certified")
+    assert n_cert > 0
+    net.close()
+
+
+# ---------------------------------------------------------------------------
+# plans: proposal path == full sweep, bit for bit
+# ---------------------------------------------------------------------------
+def _same_plans(a, b):
+    assert len(a) == len(b)
+    for i, (p, q) in enumerate(zip(a, b)):
+        assert p.status == q.status and p.n_points == q.n_points, i
+        n = p.n_points
+        assert np.array_equal(p.xyz[:n], q.xyz[:n]), i
+        assert np.array_equal(p.action[:n], q.action[:n]), i
+        assert np.array_equal(p.value[:n], q.value[:n]), i
+
+
+def _run(ctx, reqs, mode, net=None, k=8):
+    ctx.rewind()
+    ctx.set_proposal(mode, k, net)
+    plans, committed, _ = ctx.plan_fcfs(reqs)
+    return plans, committed, ctx.stats(), ctx.proposal_stats()
+
+
+def test_proposal_plans_identical_to_full_sweep(fm):
+    sc = S.large_actions(seed=2, n_plans=3000, n_requests=80)
+    A = sc.cfg.n_actions
+    net = fm.Mlp(A)
+    net.set_params(_params(A, 50))
+    with fm.context_for(sc, max_slots=64) as ctx:
+        ctx.snapshot()
+        ref, com, st, _ = _run(ctx, sc.requests, fm.PROPOSE_NONE)
+        for name, mode, nt in (("goal", fm.PROPOSE_GOAL, None), ("untrained", fm.PROPOSE_MLP, net)):
+            for k in (1, 8):
+                plans, c2, st2, ps = _run(ctx, sc.requests, mode, nt, k)
+                _same_plans(plans, ref)
+                assert np.array_equal(c2, com)
+                tot = ps["certified"] + ps["fallbacks"]
+                _log(f"[identical] {name} k={k}: {ps['certified']}/{tot} steps certified, pairs "
+                     f"{st2['pairs']:.3e} vs full {st['pairs']:.3e}")
+                assert tot > 0
+                if mode == fm.PROPOSE_GOAL and k == 8:
+                    assert ps["certified"] > 0.5 * tot
+    net.close()
+
+
+def test_training_gain_over_untrained(fm):
+    from paper_2008_03518_amd import proposal as PR
+    A = S.cfg_large_actions().n_actions
+    X, y = PR.generate_dataset([100], 60000, n_requests=150, max_slots=256, log=_log)
+    Xv, yv = PR.generate_dataset([101], 8000, n_requests=30, max_slots=64)
+    init = PR.init_params(A, seed=0)
+    untrained = fm.Mlp(A)
+    untrained.set_params(init)
+    trained = fm.Mlp(A)
+    trained.set_params(init)
+    losses = PR.train(trained, X, y, epochs=3, batch=2048, lr=2e-3, log=_log)
+    acc_u, acc_t = PR.accuracy(untrained, Xv, yv), PR.accuracy(trained, Xv, yv)
+    _log(f"[training] held-out accuracy untrained {acc_u:.3f} trained {acc_t:.3f}; losses {losses}")
+    assert losses[-1] < losses[0] and acc_t > acc_u + 0.3
+    sc = S.large_actions(seed=2, n_plans=3000, n_requests=60)
+    with fm.context_for(sc, max_slots=64) as ctx:
+        ctx.snapshot()
+        ref, com, st, _ = _run(ctx, sc.requests, fm.PROPOSE_NONE)
+        got = {}
+        for name, net in (("untrained", untrained), ("trained", trained)):
+            plans, c2, st2, ps = _run(ctx, sc.requests, fm.PROPOSE_MLP, net)
+            _same_plans(plans, ref)
+            assert np.array_equal(c2, com)
+            got[name] = ps["certified"] / max(ps["certified"] + ps["fallbacks"], 1)
+            _log(f"[training] {name}: certified {got[name]:.3f} of steps, pairs {st2['pairs']:.3e} "
+                 f"(full sweep {st['pairs']:.3e})")
+        assert got["trained"] > got["untrained"]
+    untrained.close()
+    trained.close()
