@@ -5,10 +5,15 @@ Workload: 30 x 30 x 1.5 km airspace, 3000 known straight constant-speed plans,
 steps per request, 1000 FCFS requests (seeded synthetic inputs).  One bench
 step plans and accepts all 1000 requests first-come-first-served with
 concurrent slots, starting from the 3000-plan table (rewound between steps,
-outside the timed region).  Printed: one JSON line with requests/s, the
-planner kernel's roofline against the FP32 vector peak, p50/p99 latency of a
-Poisson-arrival serving pass, and the FP64 CPU oracle timed on a bounded
-sample of the same requests.
+outside the timed region), through the whole path: the learned action
+proposal (trained beforehand, untimed, with the library's own kernels on
+1M tuples from the plain planner on scenarios of seeds 100-109) with its
+exact certificate and full-sweep fallback.  The same pass with the full
+sweep at every step is timed too, and the two must commit identical plans.
+Printed: one JSON line with requests/s, the planner kernel's roofline
+against the FP32 vector peak (for both passes), ablations of the proposal,
+p50/p99 latency of a Poisson-arrival serving pass, and the FP64 CPU oracle
+timed on a bounded sample of the same requests.
 """
 from __future__ import annotations
 
@@ -51,6 +56,65 @@ def cpu_baseline(sc, budget_s: float):
                       f"maximum), {el:.1f} s"}
 
 
+def _leg(ctx, reqs, mode, net, k, steps, warmup, name, refresh=1):
+    """Warmup + timed FCFS passes with one proposal mode; returns a dict."""
+    from paper_2008_03518_amd import fastmdp as fm
+    ctx.set_proposal(mode, k, net, refresh)
+
+    def one():
+        ctx.rewind()
+        t = time.perf_counter()
+        plans, committed, done = ctx.plan_fcfs(reqs)
+        return time.perf_counter() - t, plans, committed, ctx.stats(), ctx.proposal_stats()
+
+    for w in range(warmup):
+        el, *_ = one()
+        log(f"{name} warmup {w}: {el * 1e3:.1f} ms")
+    r = dict(times=[], pairs=0, kms=0.0, launches=0, steps=0, resumes=0, cert=0, fallback=0)
+    for i in range(steps):
+        el, plans, committed, st, ps = one()
+        r["times"].append(el)
+        for a, b in (("pairs", "pairs"), ("kms", "kernel_ms"), ("launches", "launches"), ("steps", "steps"),
+                     ("resumes", "resumes")):
+            r[a] += st[b]
+        r["cert"] += ps["certified"]
+        r["fallback"] += ps["fallbacks"]
+        log(f"{name} step {i}: {el * 1e3:.1f} ms, committed {int(committed.sum())}/{reqs.n}, pairs "
+            f"{st['pairs']:.3e}, planner {st['kernel_ms']:.1f} ms in {st['launches']} launches, resumes "
+            f"{st['resumes']}" + (f", certified {ps['certified']}/{ps['certified'] + ps['fallbacks']} steps"
+                                  if mode != fm.PROPOSE_NONE else ""))
+    r["plans"], r["committed"] = plans, committed
+    r["value"] = steps * reqs.n / sum(r["times"])
+    r["ms_per_step"] = sum(r["times"]) / steps * 1e3
+    return r
+
+
+def _roofline(r):
+    achieved = FLOPS_PER_PAIR * r["pairs"] / (r["kms"] * 1e-3) / 1e12
+    return {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": FP32_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+        "traffic": None,
+        "kernel": "planner_kernel",
+        "avg_launch_ms": r["kms"] / max(r["launches"], 1),
+        "flops_per_launch": FLOPS_PER_PAIR * r["pairs"] / max(r["launches"], 1),
+    }
+
+
+def _same_plans(a, b) -> bool:
+    for p, q in zip(a, b):
+        n = p.n_points
+        if p.status != q.status or n != q.n_points:
+            return False
+        if not (np.array_equal(p.xyz[:n], q.xyz[:n]) and np.array_equal(p.action[:n], q.action[:n])
+                and np.array_equal(p.value[:n], q.value[:n])):
+            return False
+    return len(a) == len(b)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +125,13 @@ def main():
     ap.add_argument("--slots", type=int, default=1024)
     ap.add_argument("--steps-per-launch", type=int, default=256)
     ap.add_argument("--planner-threads", type=int, default=0, help="planning workgroup size: 0 or 1024")
+    ap.add_argument("--top-k", type=int, default=8)
+    ap.add_argument("--refresh", type=int, default=4, help="steps between re-rankings of the proposal")
+    ap.add_argument("--train-tuples", type=int, default=1000000)
+    ap.add_argument("--train-epochs", type=int, default=4)
+    ap.add_argument("--params", default="", help="load trained proposal parameters (.npz) instead of training")
+    ap.add_argument("--save-params", default="", help="write the trained parameters (.npz)")
+    ap.add_argument("--ablations", type=int, default=1, help="also time goal-ranked and untrained proposals")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals [req/s]; 0 disables")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work; 0 disables")
@@ -72,87 +143,107 @@ def main():
         sys.exit(2)
 
     from paper_2008_03518_amd import fastmdp as fm
+    from paper_2008_03518_amd import proposal as PR
     from paper_2008_03518_amd import scenario as S
 
     sc = S.large_actions(seed=args.seed, n_plans=args.plans, n_requests=max(args.requests, args.serve_requests))
     cfg = sc.cfg
+    A = cfg.n_actions
     reqs = S.Requests(sc.requests.ident[:args.requests], sc.requests.origin[:args.requests],
                       sc.requests.goal[:args.requests], sc.requests.t0[:args.requests])
-    log(f"workload: {sc.plans.n} plans, {cfg.n_actions} actions, {reqs.n} requests, slots {args.slots}")
+    log(f"workload: {sc.plans.n} plans, {A} actions, {reqs.n} requests, slots {args.slots}")
+
+    # proposal network: trained (untimed) on the plain planner's choices, seeds 100-109
+    train_info = {}
+    net = fm.Mlp(A)
+    if args.params:
+        z = np.load(args.params)
+        net.set_params({k: z[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3")})
+        train_info = {"loaded": os.path.basename(args.params)}
+    else:
+        t = time.perf_counter()
+        X, y = PR.generate_dataset(range(100, 110), args.train_tuples, n_plans=args.plans, n_requests=1000,
+                                   max_slots=args.slots, log=log)
+        t_data = time.perf_counter() - t
+        net.set_params(PR.init_params(A, seed=0))
+        t = time.perf_counter()
+        losses = PR.train(net, X, y, epochs=args.train_epochs, batch=4096, lr=2e-3, log=log)
+        t_train = time.perf_counter() - t
+        train_info = {"tuples": len(X), "seeds": "100-109", "epochs": args.train_epochs, "batch": 4096,
+                      "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
+                      "data_s": t_data, "train_s": t_train}
+        del X, y
+        if args.save_params:
+            np.savez(args.save_params, **net.get_params())
 
     ctx = fm.context_for(sc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
                          planner_threads=args.planner_threads)
     ctx.snapshot()
+    full = _leg(ctx, reqs, fm.PROPOSE_NONE, None, args.top_k, args.steps, args.warmup, "full sweep")
+    prop = _leg(ctx, reqs, fm.PROPOSE_MLP, net, args.top_k, args.steps, args.warmup, "proposal", args.refresh)
+    identical = _same_plans(prop["plans"], full["plans"]) and np.array_equal(prop["committed"], full["committed"])
+    log(f"proposal plans identical to the full sweep: {identical}")
+    status = np.array([p.status for p in prop["plans"]])
 
-    def one_step():
-        ctx.rewind()
-        t = time.perf_counter()
-        plans, committed, done = ctx.plan_fcfs(reqs)
-        el = time.perf_counter() - t
-        return el, plans, committed, done, ctx.stats()
-
-    for w in range(args.warmup):
-        el, *_ = one_step()
-        log(f"warmup {w}: {el * 1e3:.1f} ms")
-    times, pairs, kms, launches, steps, resumes = [], 0, 0.0, 0, 0, 0
-    for k in range(args.steps):
-        el, plans, committed, done, st = one_step()
-        times.append(el)
-        pairs += st["pairs"]
-        kms += st["kernel_ms"]
-        launches += st["launches"]
-        steps += st["steps"]
-        resumes += st["resumes"]
-        log(f"step {k}: {el * 1e3:.1f} ms, committed {int(committed.sum())}/{reqs.n}, "
-            f"pairs {st['pairs']:.3e}, planner {st['kernel_ms']:.1f} ms in {st['launches']} launches, "
-            f"resumes {st['resumes']}")
-    total = sum(times)
-    value = args.steps * reqs.n / total
-    achieved = FLOPS_PER_PAIR * pairs / (kms * 1e-3) / 1e12
-    status = np.array([p.status for p in plans])
+    def cert_rate(r):
+        return r["cert"] / max(r["cert"] + r["fallback"], 1)
 
     out = {
         "metric": "FCFS plan requests/sec at 3000 known plans",
-        "value": value,
+        "value": prop["value"],
         "unit": "req/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": total / args.steps * 1e3,
+        "ms_per_step": prop["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{sc.plans.n} known plans, {cfg.n_actions} actions (24 headings x 5 climbs x 3 speeds), "
-                        f"dt 0.5 s, {reqs.n} FCFS requests, 30x30x1.5 km",
-            "known_plans": sc.plans.n, "actions": cfg.n_actions, "requests_per_step": reqs.n,
+            "workload": f"{sc.plans.n} known plans, {A} actions (24 headings x 5 climbs x 3 speeds), "
+                        f"dt 0.5 s, {reqs.n} FCFS requests, 30x30x1.5 km; learned proposal top-{args.top_k} "
+                        f"with exact certificate",
+            "known_plans": sc.plans.n, "actions": A, "requests_per_step": reqs.n,
             "slots": args.slots, "steps_per_launch": args.steps_per_launch,
-            "planner_threads": args.planner_threads,
+            "planner_threads": args.planner_threads, "top_k": args.top_k, "refresh": args.refresh,
         },
-        "pair_evals_per_s": pairs / (kms * 1e-3),
-        "planner_steps": steps,
-        "resumes": resumes,
-        "committed_per_step": int(committed.sum()),
+        "identical_to_full_sweep": bool(identical),
+        "pair_evals_per_s": prop["pairs"] / (prop["kms"] * 1e-3),
+        "planner_steps": prop["steps"],
+        "certified_step_rate": cert_rate(prop),
+        "resumes": prop["resumes"],
+        "committed_per_step": int(prop["committed"].sum()),
         "status_counts": {S.STATUS_NAMES[int(k)]: int((status == k).sum()) for k in np.unique(status)},
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
-            "kernel": "planner_kernel",
-            "avg_launch_ms": kms / max(launches, 1),
-            "flops_per_launch": FLOPS_PER_PAIR * pairs / max(launches, 1),
+        "roofline": _roofline(prop),
+        "full_sweep": {
+            "value": full["value"], "ms_per_step": full["ms_per_step"], "planner_steps": full["steps"],
+            "pair_evals_per_s": full["pairs"] / (full["kms"] * 1e-3), "resumes": full["resumes"],
+            "roofline": _roofline(full),
         },
+        "training": train_info,
     }
+
+    if args.ablations:
+        goal = _leg(ctx, reqs, fm.PROPOSE_GOAL, None, args.top_k, args.steps, 0, "goal-ranked", args.refresh)
+        untrained = fm.Mlp(A)
+        untrained.set_params(PR.init_params(A, seed=0))
+        unt = _leg(ctx, reqs, fm.PROPOSE_MLP, untrained, args.top_k, 1, 0, "untrained", args.refresh)
+        out["ablations"] = {
+            name: {"value": r["value"], "certified_step_rate": cert_rate(r),
+                   "identical_to_full_sweep": bool(_same_plans(r["plans"], full["plans"])),
+                   "pair_evals": r["pairs"] / len(r["times"])}
+            for name, r in (("goal_ranked_no_network", goal), ("untrained_network", unt))}
+        out["ablations"]["trained_network"] = {"value": prop["value"], "certified_step_rate": cert_rate(prop),
+                                               "pair_evals": prop["pairs"] / len(prop["times"])}
+        untrained.close()
 
     if args.serve_rate > 0:
         m = args.serve_requests
         sreq = S.Requests(sc.requests.ident[:m], sc.requests.origin[:m], sc.requests.goal[:m], sc.requests.t0[:m])
         arr = S.serving_arrivals(args.serve_rate, m, seed=3)
+        ctx.set_proposal(fm.PROPOSE_MLP, args.top_k, net, args.refresh)
         ctx.rewind()
         t = time.perf_counter()
         _, scom, sdone = ctx.plan_fcfs(sreq, arrival_s=arr)
@@ -167,6 +258,7 @@ def main():
         log(f"serving at {args.serve_rate} req/s: p50 {out['p50_latency_ms']:.1f} ms, "
             f"p99 {out['p99_latency_ms']:.1f} ms")
     ctx.close()
+    net.close()
 
     if args.cpu_budget > 0:
         log("cpu baseline (oracle) ...")

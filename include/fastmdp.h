@@ -81,7 +81,8 @@ typedef struct {
     int32_t n_head, n_climb, n_speed;
     double climb[FASTMDP_MAX_ACT_DIM];   /* [m/s], n_climb used                   */
     double speed[FASTMDP_MAX_ACT_DIM];   /* [m/s], n_speed used, all > 0          */
-    int32_t max_steps;               /* steps per request (<= max_steps+1 points) */
+    int32_t max_steps;               /* steps per request (<= max_steps+1 points),
+                                        at most 16383                             */
     int32_t plan_capacity;           /* known-plan entries per time row           */
     int32_t max_rows;                /* time rows in the table                    */
     int32_t max_slots;               /* requests planned concurrently (>= 1)      */
@@ -308,12 +309,16 @@ int fastmdp_features(fastmdp_ctx *ctx, int32_t n, const double *states, const do
 int fastmdp_next_seq(const fastmdp_ctx *ctx);
 
 /* Select the proposal for later planning calls: mode FASTMDP_PROPOSE_*,
- * 1 <= top_k <= FASTMDP_MAX_TOPK.  FASTMDP_PROPOSE_MLP needs a network with
- * n_in = FASTMDP_N_FEAT, n_hidden = FASTMDP_MLP_HIDDEN and n_out >= the
- * number of actions, on the same device; the context reads its current
- * weights at every step, so it must stay alive (and untrained, if the plans
- * are to be repeatable) while selected.  Errors: E_INVAL. */
-int fastmdp_set_proposal(fastmdp_ctx *ctx, int32_t mode, int32_t top_k, const fastmdp_mlp *net);
+ * 1 <= top_k <= FASTMDP_MAX_TOPK.  The ranking and its top_k are recomputed
+ * every `refresh` steps (>= 1; 1 = every step) and after every step that
+ * fell back to the full sweep; in between the same actions (relative to the
+ * goal bearing) are scored exactly, and the certificate is decided at every
+ * step, so plans do not depend on refresh.  FASTMDP_PROPOSE_MLP needs a
+ * network with n_in = FASTMDP_N_FEAT, n_hidden = FASTMDP_MLP_HIDDEN and
+ * n_out >= the number of actions, on the same device; the context reads its
+ * current weights at every ranking, so it must stay alive while selected.
+ * Errors: E_INVAL. */
+int fastmdp_set_proposal(fastmdp_ctx *ctx, int32_t mode, int32_t top_k, int32_t refresh, const fastmdp_mlp *net);
 
 /* The proposal at one state (as fastmdp_eval_step): features (HOST
  * FASTMDP_N_FEAT) and logits (HOST, one per action), both

@@ -97,7 +97,7 @@ void free_all(fastmdp_ctx *c) {
     hipFree(c->dTerr);
     hipFree(c->dSlots); hipFree(c->dList); hipFree(c->dOrder); hipFree(c->dNdone);
     hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen); hipFree(c->tr.top);
-    hipFree(c->tr.ep); hipFree(c->tr.col);
+    hipFree(c->tr.ep); hipFree(c->tr.col); hipFree(c->tr.nd);
     hipFree(c->dEv); hipFree(c->dBest); hipFree(c->dPts); hipFree(c->dFlag);
     if (c->hSlots) hipHostFree(c->hSlots);
     if (c->hGather) hipHostFree(c->hGather);
@@ -119,7 +119,8 @@ int check_cfg(const fastmdp_config *c) {
         return FASTMDP_E_INVAL;
     for (int v = 0; v < c->n_speed; ++v)
         if (!(c->speed[v] > 0.0)) return FASTMDP_E_INVAL;
-    if (c->max_steps < 1 || c->plan_capacity < 1 || c->max_rows < 2) return FASTMDP_E_INVAL;
+    if (c->max_steps < 1 || c->max_steps + 1 > fmdp::kMaxPoints || c->plan_capacity < 1 || c->max_rows < 2)
+        return FASTMDP_E_INVAL;
     if (!(c->tie_rel >= 0.0)) return FASTMDP_E_INVAL;
     if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads) return FASTMDP_E_INVAL;
     return 0;
@@ -309,6 +310,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->tr.top, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.ep, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.col, ssz);
+    rc = rc ? rc : dev_alloc(&c->tr.nd, ssz);
     c->dl_cap = 1 << 22;
     c->dl_start_cap = 1 << 16;
     rc = rc ? rc : dev_alloc(&c->dDlRow, (size_t)c->dl_cap);
@@ -676,11 +678,12 @@ int fastmdp_features(fastmdp_ctx *ctx, int32_t n, const double *states, const do
 
 int fastmdp_next_seq(const fastmdp_ctx *ctx) { return ctx ? ctx->seq : FASTMDP_E_INVAL; }
 
-int fastmdp_set_proposal(fastmdp_ctx *ctx, int32_t mode, int32_t top_k, const fastmdp_mlp *net) {
-    if (!ctx) return FASTMDP_E_INVAL;
+int fastmdp_set_proposal(fastmdp_ctx *ctx, int32_t mode, int32_t top_k, int32_t refresh, const fastmdp_mlp *net) {
+    if (!ctx || refresh < 1) return FASTMDP_E_INVAL;
     fmdp::PropArgs p{};
     p.mode = mode;
     p.k = top_k;
+    p.refresh = refresh;
     if (mode == FASTMDP_PROPOSE_NONE) {
         p.k = 0;
     } else if (mode == FASTMDP_PROPOSE_MLP || mode == FASTMDP_PROPOSE_GOAL) {

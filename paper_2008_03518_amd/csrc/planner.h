@@ -10,7 +10,9 @@
 namespace fmdp {
 
 constexpr int kPlanThreads = 1024;  // planning workgroup: one request per CU, 16 wave64
+constexpr int kPropThreads = 512;   // with the proposal path: 8 wave64, twice the registers per lane
 constexpr int kMaxActions = 512;
+constexpr int kMaxPoints = 4 * 4096;  // trajectory points per request (the validation list reuses the tile)
 constexpr int kMaxHeads = 128;
 constexpr int kRunning = -1;        // slot status while a request is being planned
 constexpr int kAlive = 0x7fffffff;  // table entry death epoch of a live entry
@@ -82,7 +84,8 @@ struct Slot {
 // which that scoring is known to be consistent.  top[k] is the action with
 // the largest value at that step when the chosen action (the lowest index
 // inside the tie band) is not itself the largest, else -1.  col[k] is the
-// column of point k's tentative table entry, -1 if none.
+// column of point k's tentative table entry, -1 if none.  nd[k] is the
+// nearest-plan squared distance of point k as the step scored it.
 struct Traj {
     double *xyz;
     int *act;
@@ -91,6 +94,8 @@ struct Traj {
     int *ep;
     int *top;
     int *col;
+    double *nd;      // squared distance from point k to the nearest plan of its row, as scored
+                     // (infinity for the origin, which the origin check validated exactly)
     int stride;
 };
 
@@ -119,9 +124,10 @@ struct PropNet {
     int n_in, n_hid, n_out;
 };
 
-// Proposal selection of a planner launch (mode FASTMDP_PROPOSE_*).
+// Proposal selection of a planner launch (mode FASTMDP_PROPOSE_*): the top
+// k of the ranking, re-ranked every `refresh` steps and after a fallback.
 struct PropArgs {
-    int mode, k;
+    int mode, k, refresh;
     PropNet net;
 };
 

@@ -23,6 +23,7 @@
 //      ("Determine terminal state").
 #include "planner.h"
 #include "proposal.h"
+#include "wave.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -56,16 +57,23 @@ struct Scored {
     double clr;         // terrain clearance (inf without terrain)
 };
 
+// Per-speed step length speed*dt and per-climb altitude change climb*dt
+// (FP64), kept in LDS: indexed per lane, a lookup in the kernel-argument
+// block would be a vector memory load.
+struct ActTab {
+    const double *step, *dz;
+};
+
 // Successor of state s under action a, whose heading has unit direction
 // (dx, dy).
-__device__ __forceinline__ void successor(const DevCfg &c, int a, const double s[3], double dx, double dy, double &x,
-                                          double &y, double &z) {
+__device__ __forceinline__ void successor(const DevCfg &c, const ActTab &at, int a, const double s[3], double dx,
+                                          double dy, double &x, double &y, double &z) {
     const int v = a % c.n_speed;
     const int cl = (a / c.n_speed) % c.n_climb;
-    const double step = c.speed[v] * c.dt;
+    const double step = at.step[v];
     x = s[0] + step * dx;
     y = s[1] + step * dy;
-    z = s[2] + c.climb[cl] * c.dt;
+    z = s[2] + at.dz[cl];
 }
 
 // Goal peak r_goal * gamma^(d/ell) at a successor.  Every action's value is
@@ -79,18 +87,18 @@ __device__ __forceinline__ double goal_term(const DevCfg &c, double x, double y,
 // Squared distance from action a's successor to the nearest plan, from the
 // sweep's minimum m of |q|^2 - 2 Delta . q over the staged plans.
 template <int NC, int NV>
-__device__ __forceinline__ double nearest_d2(const DevCfg &c, int a, float m) {
-    const double step = c.speed[a % NV] * c.dt;
-    const double dz = c.climb[(a / NV) % NC] * c.dt;
+__device__ __forceinline__ double nearest_d2(const ActTab &at, int a, float m) {
+    const double step = at.step[a % NV];
+    const double dz = at.dz[(a / NV) % NC];
     return fma(dz, dz, fma(step, step, (double)m));
 }
 
 // Score action a from state s: dx, dy is its heading's unit direction and
 // d2 the squared distance from the successor to the nearest plan.
-__device__ Scored score_action(const DevCfg &c, const DevTable &tb, int a, const double s[3], const double g[3],
-                               double dx, double dy, double d2) {
+__device__ Scored score_action(const DevCfg &c, const DevTable &tb, const ActTab &at, int a, const double s[3],
+                               const double g[3], double dx, double dy, double d2) {
     Scored r;
-    successor(c, a, s, dx, dy, r.x, r.y, r.z);
+    successor(c, at, a, s, dx, dy, r.x, r.y, r.z);
     r.G = goal_term(c, r.x, r.y, r.z, g);
     r.I = 0.0;
     if (d2 < c.R_intr * c.R_intr) r.I = c.abs_r_intr * exp(c.log_gamma_intr * (sqrt(fmax(d2, 0.0)) / c.ell));
@@ -111,26 +119,19 @@ __device__ Scored score_action(const DevCfg &c, const DevTable &tb, int a, const
 // in the step loop is read back only after a full __syncthreads.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-    return v;
-}
+__device__ __forceinline__ double wave_max(double v) { return wave_max_f64(v); }
+__device__ __forceinline__ float wave_maxf(float v) { return wave_max_f32(v); }
+__device__ __forceinline__ int wave_min(int v) { return wave_min_i32(v); }
 
-__device__ __forceinline__ float wave_maxf(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    return v;
-}
+// Relative margin that makes the FP32 goal term an upper bound of the FP64
+// one: the FP32 exponent r*log2(gamma)*d/ell carries a relative error of a few
+// 1e-7 (distance, constants, roundings), i.e. an absolute error below 1.2e-5
+// for exponents up to 40 (over 50 km at 20 m per step), and the result a
+// relative error below 1e-5; 1e-4 leaves a factor of ten.
+constexpr float kGoalBoundRel = 1e-4f;
 
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const int o = __shfl_xor(v, off);
-        v = o < v ? o : v;
-    }
-    return v;
-}
+// Longest run of steps the proposal sits out after repeated fallbacks.
+constexpr int kMaxBackoff = 16;
 
 template <int NT>
 struct PlanGeom {
@@ -147,6 +148,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     constexpr int NW = Geo::NW, TILE = Geo::TILE, PRE = Geo::PRE;
     constexpr int KMAX = FASTMDP_MAX_TOPK, HID = FASTMDP_MLP_HIDDEN;
     __shared__ float4 tile[TILE];               // staged plans; reused for the slice partial minima
+    __shared__ float rawX[TILE], rawY[TILE], rawZ[TILE];   // the next row chunk as read from the table
+    __shared__ int rawK[TILE];                             // its visibility keys
     __shared__ double sV[kMaxActions];          // FP64 values of the candidate actions
     __shared__ double sD2[kMaxActions];         // squared nearest-plan distance per action
     __shared__ float sLo[kMaxActions], sHi[kMaxActions];   // FP32 value brackets
@@ -162,11 +165,15 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ FeatAcc sFa;                                      // traffic feature accumulators
     __shared__ __attribute__((aligned(16))) uint16_t sAct[3][HID];   // BF16 features, hidden 1, hidden 2
     __shared__ float sKey[kMaxActions];                          // ranking key per action
-    __shared__ double sG[kMaxActions];                           // goal-term bound per action
+    __shared__ float sGu[kMaxActions];                           // goal-term upper bound per action
     __shared__ unsigned sInK[kMaxActions / 32];                  // proposed-set membership
     __shared__ int sK[KMAX];                                     // proposed actions, best first
     __shared__ float sKm[NW][KMAX];                              // per-wave nearest minima
     __shared__ int st_cert, st_best, st_top;
+    __shared__ double st_r[6];                                   // certified choice: x, y, z, V, I, clearance
+    __shared__ double sStep[FASTMDP_MAX_ACT_DIM], sDz[FASTMDP_MAX_ACT_DIM];   // speed*dt, climb*dt
+    __shared__ float sKv[FASTMDP_MAX_ACT_DIM], sClf[FASTMDP_MAX_ACT_DIM];      // FP32 sweep constants
+    const ActTab at{sStep, sDz};
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -178,7 +185,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     const int n_slices = NT / H;
     const int my_h = tid % H, my_slice = tid / H;
     const bool sweeper = tid < n_slices * H;
-    const int tcap = (TILE / (2 * n_slices)) * (2 * n_slices);   // whole sweep rounds per tile
+    const int tcap = TILE;                                        // row entries per chunk
     const int n_part = n_slices;                                  // slice partial minima per action
 
     const double g[3] = {S.goal[0], S.goal[1], S.goal[2]};
@@ -190,6 +197,12 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         const double th = 2.0 * M_PI * (double)h / (double)H;
         sC0[h] = cos(th);
         sS0[h] = sin(th);
+    }
+    if (tid < FASTMDP_MAX_ACT_DIM) {
+        sStep[tid] = cfg.speed[tid] * cfg.dt;
+        sDz[tid] = cfg.climb[tid] * cfg.dt;
+        sKv[tid] = cfg.kv[tid];
+        sClf[tid] = cfg.climb_f[tid];
     }
     if constexpr (PROP) feat_reset(sFa, tid);
     if (tid == 0) {
@@ -231,64 +244,63 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             tr.ep[pt_base] = epoch;
             tr.top[pt_base] = -1;
             tr.col[pt_base] = -1;
+            tr.nd[pt_base] = INFINITY;
             st_n = 1;
             if (blocked) st_status = FASTMDP_REJECT_ORIGIN;
         }
         __syncthreads();
     }
 
-    // per-lane sweep constants
-    float kv[NV], clf[NC];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) kv[v] = cfg.kv[v];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) clf[c] = cfg.climb_f[c];
-
-    // One chunk of a row (up to tcap entries) in registers: entry
-    // base + tid + i*NT with its visibility key, left unevaluated until
-    // staging so that the loads are not waited for where they are issued.
-    // The first chunk of the next step's row is loaded during the sweep
-    // (the barriers of the step loop do not wait for it).
-    float px[PRE], py[PRE], pz[PRE];
-    int pk[PRE];
-    int pre_n = 0;
+    // One chunk of a row (up to tcap entries) travels from the table to LDS
+    // without registers (global_load_lds): entry base + j, j = i*NT +
+    // wave*64 + lane, lands at raw*[j].  Each wave later stages exactly the
+    // entries its own loads brought (thread tid takes j = tid + i*NT), so it
+    // only waits for its own loads (vmcnt), with no barrier, and may issue
+    // the next row's loads as soon as it has staged this one.  The first
+    // chunk of the next step's row is in flight during the sweep.
+    int pre_n = 0, pre_lim = 0;
     auto load_chunk = [&](int row, int base) {
-        const size_t rb = (size_t)row * tb.cap;
+        const size_t rb = (size_t)row * tb.cap + base;
         const int lim = min(pre_n - base, tcap);
+        pre_lim = lim;
+        // the per-lane offset is made opaque so that the addresses are formed
+        // here (one add each) instead of being hoisted out of the step loop,
+        // where they would occupy 32 registers and be spilled
+        int ofs = tid;
+        asm volatile("" : "+v"(ofs));
 #pragma unroll
         for (int i = 0; i < PRE; ++i) {
-            const int j = tid + i * NT;
-            pk[i] = kAlive;                                // invisible unless loaded
+            const int j0 = i * NT + wave * 64;             // wave-uniform LDS destination
+            const int j = ofs + i * NT;
             if (j < lim) {
-                const size_t idx = rb + base + j;
-                px[i] = tb.X[idx];
-                py[i] = tb.Y[idx];
-                pz[i] = tb.Z[idx];
-                pk[i] = tb.vis[idx];
+                __builtin_amdgcn_global_load_lds(tb.X + rb + j, rawX + j0, 4, 0, 0);
+                __builtin_amdgcn_global_load_lds(tb.Y + rb + j, rawY + j0, 4, 0, 0);
+                __builtin_amdgcn_global_load_lds(tb.Z + rb + j, rawZ + j0, 4, 0, 0);
+                __builtin_amdgcn_global_load_lds(tb.vis + rb + j, rawK + j0, 4, 0, 0);
             }
         }
     };
     auto row_count = [&](int row) { return (row >= 0 && row < tb.rows) ? min(tb.rowN[row], tb.cap) : 0; };
-    // Stage the chunk in registers into LDS, compacted to the entries this
-    // request sees, as (q_x, q_y, -2 dt q_z, |q|^2) with q = p - s; pad to
-    // whole sweep rounds with entries at infinity.  Returns the count.
+    // Stage the chunk into the tile, compacted to the entries this request
+    // sees, as (q_x, q_y, -2 dt q_z, |q|^2) with q = p - s.  Returns the
+    // count.
     auto stage_chunk = [&](const double s[3]) -> int {
+        // wave-level compaction with ballots: entry i of this lane goes after
+        // the wave's visible entries of lower i and of lower lanes at i
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of the chunk landed
         bool pv[PRE];
-        int cnt = 0;
+        uint64_t bal[PRE];
+        int wcnt = 0;
 #pragma unroll
         for (int i = 0; i < PRE; ++i) {
-            pv[i] = pk[i] < seq;
-            cnt += pv[i] ? 1 : 0;
+            const int j = tid + i * NT;
+            pv[i] = j < pre_lim && rawK[j] < seq;
+            bal[i] = __ballot(pv[i]);
+            wcnt += __popcll(bal[i]);
         }
-        int x = cnt;                                       // inclusive wave scan
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) s_wsum[wave] = x;
+        if (lane == 0) s_wsum[wave] = wcnt;
         lds_barrier();
-        int pos = x - cnt, total = 0;
+        int pos = 0, total = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const int t = s_wsum[w];
@@ -296,15 +308,18 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             total += t;
         }
 #pragma unroll
-        for (int i = 0; i < PRE; ++i)
+        for (int i = 0; i < PRE; ++i) {
             if (pv[i]) {
-                const float qx = (float)((double)px[i] - s[0]);
-                const float qy = (float)((double)py[i] - s[1]);
-                const float qz = (float)((double)pz[i] - s[2]);
-                tile[pos++] = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+                const int j = tid + i * NT;
+                const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[i] >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal[i], 0));
+                const float qx = (float)((double)rawX[j] - s[0]);
+                const float qy = (float)((double)rawY[j] - s[1]);
+                const float qz = (float)((double)rawZ[j] - s[2]);
+                tile[pos + below] = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
             }
-        const int npad = ((total + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
-        for (int j = total + tid; j < npad; j += NT) tile[j] = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+            pos += __popcll(bal[i]);
+        }
         return total;
     };
     // Actions whose FP32 nearest distance lies within kBand of the well
@@ -317,9 +332,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 const int a = w * 32 + __builtin_ctz(bits);
                 bits &= bits - 1;
                 const int h = a / (NC * NV);
-                const double step = cfg.speed[a % NV] * cfg.dt;
-                const double qx = s[0] + step * sCos[h], qy = s[1] + step * sSin[h];
-                const double qz = s[2] + cfg.climb[(a / NV) % NC] * cfg.dt;
+                double qx, qy, qz;
+                successor(cfg, at, a, s, sCos[h], sSin[h], qx, qy, qz);
                 double dmin = INFINITY;
                 for (int j = tid; j < n_row; j += NT)
                     if (entry_visible(tb, rb + j, seq))
@@ -344,6 +358,12 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
 
     long long pairs = 0;
     int steps_here = 0, hits = 0, misses = 0;
+    int since = 1 << 30;                                         // steps since the last ranking
+    // after a step that fell back, the proposal sits out `skip` steps (the
+    // full sweep runs directly), doubling up to kMaxBackoff while it keeps
+    // failing: inside traffic the certificate rarely holds and the attempt
+    // would only add to the full sweep's cost
+    int skip = 0, backoff = 1;
 
     for (;;) {
         if (st_status != kRunning) break;                 // uniform (LDS, after a barrier)
@@ -387,7 +407,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         // top k exactly with the full sweep's arithmetic, and take the step
         // from them when the certificate holds.
         if constexpr (PROP) {
-            if (prop.mode != FASTMDP_PROPOSE_NONE && single) {
+            if (prop.mode != FASTMDP_PROPOSE_NONE && single && (skip == 0 || eval)) {
                 if (n_row > 0) n_vis = stage_chunk(s);
                 if (!eval) {                               // next row in flight meanwhile
                     pre_n = n_next;
@@ -396,18 +416,35 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 staged = true;
                 const int K = min(prop.k, A);
                 if (n_row == 0) lds_barrier();             // headings visible (staging has its own barrier)
-                // goal-term bound of every action (-inf outside the box)
-                for (int a = tid; a < A; a += NT) {
-                    const int h = a / (NC * NV);
-                    double x, y, z;
-                    successor(cfg, a, s, sCos[h], sSin[h], x, y, z);
-                    const double G = outside_box(cfg, x, y, z) ? -INFINITY : goal_term(cfg, x, y, z, g);
-                    sG[a] = G;
-                    if (prop.mode == FASTMDP_PROPOSE_GOAL) sKey[a] = (float)G;
+                // the ranking (and the proposed set) is refreshed every
+                // prop.refresh steps and after every fallback; the certificate
+                // is decided at every step
+                const bool rank = eval || since >= prop.refresh;
+                // upper bound of every action's goal term (FP32 with a margin;
+                // -inf outside the box, decided in FP64)
+                {
+                    const float gx32 = (float)(g[0] - s[0]), gy32 = (float)(g[1] - s[1]);
+                    const float gz32 = (float)(g[2] - s[2]);
+                    for (int a = tid; a < A; a += NT) {
+                        const int h = a / (NC * NV);
+                        double x, y, z;
+                        successor(cfg, at, a, s, sCos[h], sSin[h], x, y, z);
+                        float gu = -INFINITY;
+                        if (!outside_box(cfg, x, y, z)) {
+                            const float ex = gx32 - (float)(x - s[0]), ey = gy32 - (float)(y - s[1]);
+                            const float ez = gz32 - (float)(z - s[2]);
+                            gu = cfg.abs_r_goal_f *
+                                 exp2f(cfg.log2_gamma_f * (sqrtf(ex * ex + ey * ey + ez * ez) * cfg.inv_ell_f)) *
+                                 (1.0f + kGoalBoundRel);
+                        }
+                        sGu[a] = gu;
+                        if (rank && prop.mode == FASTMDP_PROPOSE_GOAL) sKey[a] = gu;
+                    }
                 }
-                for (int w = tid; w < kMaxActions / 32; w += NT) sInK[w] = 0u;
+                if (rank)
+                    for (int w = tid; w < kMaxActions / 32; w += NT) sInK[w] = 0u;
                 lds_barrier();                             // tile staged, headings visible
-                if (prop.mode == FASTMDP_PROPOSE_MLP) {
+                if (rank && prop.mode == FASTMDP_PROPOSE_MLP) {
                     const float ux = (float)cb, uy = (float)sb;
                     for (int j = tid; j < n_vis; j += NT) {
                         const float4 p = tile[j];
@@ -424,23 +461,29 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     // three layers, one 16-neuron tile per wave at a time:
                     // the state vector is broadcast to every row of the MFMA A
                     // operand, the weights [out][in] are the B operand, row 0
-                    // of the result (lanes 0-15, register 0) is the layer.
+                    // of the result (lanes 0-15, register 0) is the layer.  All
+                    // of a tile's weight loads are issued before its MFMAs.
                     const PropNet &W = prop.net;
                     for (int layer = 0; layer < 3; ++layer) {
                         const int kin = layer == 0 ? FASTMDP_N_FEAT : HID;
+                        const int nk = kin / 32;
                         const int nout = layer == 2 ? A : HID;
                         const uint16_t *Wl = layer == 0 ? W.W1 : (layer == 1 ? W.W2 : W.W3);
                         const float *bl = layer == 0 ? W.b1 : (layer == 1 ? W.b2 : W.b3);
                         const uint16_t *in = sAct[layer];
+                        const int kofs = 8 * (lane >> 4);
                         for (int tl = wave; tl * 16 < nout; tl += NW) {
                             const int nn = tl * 16 + (lane & 15);
-                            const int kofs = 8 * (lane >> 4);
+                            const uint4 *wrow = reinterpret_cast<const uint4 *>(Wl + (size_t)nn * kin + kofs);
+                            uint4 wv[HID / 32];
+#pragma unroll
+                            for (int q = 0; q < HID / 32; ++q)
+                                if (q < nk) wv[q] = wrow[4 * q];
                             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                            for (int k0 = 0; k0 < kin; k0 += 32) {
-                                const uint4 av = *reinterpret_cast<const uint4 *>(in + k0 + kofs);
-                                const uint4 wv = *reinterpret_cast<const uint4 *>(Wl + (size_t)nn * kin + k0 + kofs);
-                                acc = mfma_bf16(av, wv, acc);
-                            }
+#pragma unroll
+                            for (int q = 0; q < HID / 32; ++q)
+                                if (q < nk)
+                                    acc = mfma_bf16(*reinterpret_cast<const uint4 *>(in + 32 * q + kofs), wv[q], acc);
                             if (lane < 16 && nn < nout) {
                                 const float z = acc[0] + bl[nn];
                                 if (layer < 2) {
@@ -455,49 +498,68 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     }
                 }
                 // top K by key (largest first, lowest index on ties; NaN
-                // ranks last), one wave
-                if (wave == 0) {
-                    float key[kMaxActions / 64];
+                // ranks last), one wave: keys packed with the complement of
+                // the index into 64 bits and sorted within each lane once;
+                // each round takes the wave maximum of the lanes' heads
+                if (rank && wave == 0) {
+                    constexpr int KPL = kMaxActions / 64;
+                    uint64_t kk[KPL];
 #pragma unroll
-                    for (int i = 0; i < kMaxActions / 64; ++i) {
+                    for (int i = 0; i < KPL; ++i) {
                         const int a = lane + 64 * i;
-                        const float v = a < A ? sKey[a] : -INFINITY;
-                        key[i] = (v == v) ? v : -INFINITY;
+                        kk[i] = a < A ? ((uint64_t)ordered_f32(sKey[a]) << 32) | (0xffffffffu - (uint32_t)a) : 0u;
                     }
-                    unsigned taken = 0u;
+                    auto cas = [&](int i, int j) {         // descending
+                        const uint64_t x = kk[i], y = kk[j];
+                        kk[i] = x > y ? x : y;
+                        kk[j] = x > y ? y : x;
+                    };
+                    // Batcher's odd-even merge network for 8 keys
+                    cas(0, 1); cas(2, 3); cas(4, 5); cas(6, 7);
+                    cas(0, 2); cas(1, 3); cas(4, 6); cas(5, 7);
+                    cas(1, 2); cas(5, 6);
+                    cas(0, 4); cas(1, 5); cas(2, 6); cas(3, 7);
+                    cas(2, 4); cas(3, 5);
+                    cas(1, 2); cas(3, 4); cas(5, 6);
                     for (int r = 0; r < K; ++r) {
-                        float bv = -INFINITY;
-                        int bi = 0x7fffffff;
+                        const uint64_t m = wave_max_u64(kk[0]);
+                        const int a = (int)(0xffffffffu - (uint32_t)m);
+                        if (kk[0] == m) {
 #pragma unroll
-                        for (int i = 0; i < kMaxActions / 64; ++i) {
-                            const int a = lane + 64 * i;
-                            if (a < A && !(taken >> i & 1u) && (key[i] > bv || bi == 0x7fffffff)) {
-                                bv = key[i];
-                                bi = a;
-                            }
+                            for (int i = 0; i + 1 < KPL; ++i) kk[i] = kk[i + 1];
+                            kk[KPL - 1] = 0u;
                         }
-#pragma unroll
-                        for (int off = 32; off > 0; off >>= 1) {
-                            const float ov = __shfl_xor(bv, off);
-                            const int oi = __shfl_xor(bi, off);
-                            if (oi != 0x7fffffff && (bi == 0x7fffffff || ov > bv || (ov == bv && oi < bi))) {
-                                bv = ov;
-                                bi = oi;
-                            }
-                        }
-                        if ((bi & 63) == lane) taken |= 1u << (bi >> 6);
                         if (lane == 0) {
-                            sK[r] = bi;
-                            sInK[bi >> 5] |= 1u << (bi & 31);
-                            if (ev.topk) ev.topk[r] = bi;
+                            sK[r] = a;
+                            if (ev.topk) ev.topk[r] = a;
                         }
                     }
                 }
-                lds_barrier();
+                if (rank) {
+                    lds_barrier();
+                    if (wave == 0 && lane < K) {
+                        const int a = sK[lane];
+                        atomicOr(&sInK[a >> 5], 1u << (a & 31));
+                    }
+                    since = 0;
+                }
+                since += 1;
                 // exact nearest distances of the K actions: the sweep's FP32
                 // expression over the same staged plans (min is exact, so
-                // the result does not depend on the order)
+                // the result does not depend on the order).  Lane r holds the
+                // constants of action r; each round broadcasts them.
                 {
+                    float kch = 0.0f, ksh = 0.0f, kkv = 0.0f, kclf = 0.0f;
+                    int kzc = 0;
+                    if (lane < K) {
+                        const int a = sK[lane];
+                        const int h = a / (NC * NV), c = (a / NV) % NC, v = a % NV;
+                        kch = (float)sCos[h];
+                        ksh = (float)sSin[h];
+                        kkv = sKv[v];
+                        kclf = sClf[c];
+                        kzc = c == ZC;
+                    }
                     float4 pe[PRE];
 #pragma unroll
                     for (int i = 0; i < PRE; ++i) {
@@ -505,20 +567,20 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                         pe[i] = j < n_vis ? tile[j] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
                     }
                     for (int r = 0; r < K; ++r) {
-                        const int a = sK[r];
-                        const int h = a / (NC * NV), c = (a / NV) % NC, v = a % NV;
-                        const float ch = (float)sCos[h], sh = (float)sSin[h];
-                        const float kvv = cfg.kv[v], clv = cfg.climb_f[c];
+                        const float ch = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kch), r));
+                        const float sh = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ksh), r));
+                        const float kvv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kkv), r));
+                        const float clv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kclf), r));
+                        const int zc = __builtin_amdgcn_readlane(kzc, r);
                         float m = INFINITY;
 #pragma unroll
                         for (int i = 0; i < PRE; ++i) {
                             const float hq = fmaf(pe[i].x, ch, pe[i].y * sh);
                             const float u = fmaf(kvv, hq, pe[i].w);
-                            const float d = (c == ZC) ? u : fmaf(clv, pe[i].z, u);
+                            const float d = zc ? u : fmaf(clv, pe[i].z, u);
                             m = fminf(m, d);
                         }
-#pragma unroll
-                        for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
+                        m = wave_min_f32(m);
                         if (lane == 0) sKm[wave][r] = m;
                     }
                 }
@@ -529,7 +591,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     const int a = sK[lane];
                     float m = INFINITY;
                     for (int w = 0; w < NW; ++w) m = fminf(m, sKm[w][lane]);
-                    const double d2 = nearest_d2<NC, NV>(cfg, a, m);
+                    const double d2 = nearest_d2<NC, NV>(at, a, m);
                     sD2[a] = d2;
                     if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) {
                         atomicOr(&sBand[a >> 5], 1u << (a & 31));
@@ -543,30 +605,51 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (tid == 0) s_any = 0;
                 if (any_band) band_recheck(s, n_row, rb);
                 // certificate: the best exact value among the K, less the tie
-                // band, must exceed every other action's goal term
+                // band, must exceed an upper bound of every other action's
+                // goal term, hence of its value
                 if (wave == 0) {
                     double v = -INFINITY;
                     int a = 0x7fffffff;
+                    Scored sc{};
                     if (lane < K) {
                         a = sK[lane];
                         const int h = a / (NC * NV);
-                        v = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]).V;
+                        sc = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]);
+                        v = sc.V;
                     }
                     const double vm = wave_max(v);
                     const double thr = vm - cfg.tie_rel * fabs(vm);
-                    double tau = -INFINITY;
+                    float tau = -INFINITY;
                     for (int b = lane; b < A; b += 64)
-                        if (!(sInK[b >> 5] >> (b & 31) & 1u)) tau = fmax(tau, sG[b]);
-                    tau = wave_max(tau);
-                    const int ok = vm > -INFINITY && tau < thr;
+                        if (!(sInK[b >> 5] >> (b & 31) & 1u)) tau = fmaxf(tau, sGu[b]);
+                    tau = wave_maxf(tau);
+                    int ok = vm > -INFINITY && (double)tau < thr;
+                    // the FP32 bound is loose by up to 1e-4: where it does not
+                    // clear the threshold but the exact goal term might, decide
+                    // with the exact term (the one the value is computed from)
+                    if (!ok && vm > -INFINITY && (double)tau * (1.0 - 4.0 * kGoalBoundRel) < thr) {
+                        int bad = 0;
+                        for (int b = lane; b < A; b += 64)
+                            if (!(sInK[b >> 5] >> (b & 31) & 1u) && (double)sGu[b] >= thr) {
+                                const int h = b / (NC * NV);
+                                double x, y, z;
+                                successor(cfg, at, b, s, sCos[h], sSin[h], x, y, z);
+                                if (!(goal_term(cfg, x, y, z, g) < thr)) bad = 1;
+                            }
+                        ok = __ballot(bad) == 0;
+                    }
                     const int best = wave_min(lane < K && v >= thr ? a : 0x7fffffff);
                     const int top1 = wave_min(lane < K && v == vm ? a : 0x7fffffff);
                     const double vb = wave_max(lane < K && a == best ? v : -INFINITY);
+                    if (ok && lane < K && a == best) {             // the advance reuses the scoring
+                        st_r[0] = sc.x; st_r[1] = sc.y; st_r[2] = sc.z;
+                        st_r[3] = sc.V; st_r[4] = sc.I; st_r[5] = sc.clr;
+                    }
                     if (lane == 0) {
                         st_cert = ok;
                         st_best = best;
                         st_top = vb < vm ? top1 : -1;
-                        pairs += (long long)(K + (prop.mode == FASTMDP_PROPOSE_MLP ? 1 : 0)) * n_vis;
+                        pairs += (long long)(K + (rank && prop.mode == FASTMDP_PROPOSE_MLP ? 1 : 0)) * n_vis;
                         if (eval) {
                             if (ev.cert) *ev.cert = ok;
                             if (ev.pbest) *ev.pbest = ok ? best : -1;
@@ -575,12 +658,22 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 }
                 lds_barrier();
                 cert = eval ? 0 : st_cert;                 // eval always runs the full sweep too
+                if (!eval) {
+                    if (cert) {
+                        backoff = 1;
+                    } else {
+                        since = prop.refresh;              // re-rank at the next attempt
+                        skip = backoff;
+                        backoff = min(2 * backoff, kMaxBackoff);
+                    }
+                }
                 if (tid == 0 && !eval) {
                     if (cert) ++hits;
                     else ++misses;
                 }
-            } else if (prop.mode != FASTMDP_PROPOSE_NONE && tid == 0 && !eval) {
-                ++misses;                                  // row larger than one tile: full sweep
+            } else if (prop.mode != FASTMDP_PROPOSE_NONE && !eval) {
+                if (skip > 0) --skip;
+                if (tid == 0) ++misses;                    // backing off, or a row larger than one tile
             }
         }
 
@@ -589,6 +682,11 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             //      lane, one heading's climb x speed actions over a slice of the
             //      staged plans (two plans per round: v_min3)
             float ch = 0.0f, sh = 0.0f;
+            float kv[NV], clf[NC];                           // per-lane sweep constants
+#pragma unroll
+            for (int v = 0; v < NV; ++v) kv[v] = sKv[v];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) clf[c] = sClf[c];
             float acc[NC][NV];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -615,24 +713,30 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     ch = (float)sCos[my_h];
                     sh = (float)sSin[my_h];
                 }
-                const int npad = ((nv + 2 * n_slices - 1) / (2 * n_slices)) * (2 * n_slices);
-                if (sweeper) {
-                    for (int i = my_slice; i < npad; i += 2 * n_slices) {
-                        const float4 p0 = tile[i];
-                        const float4 p1 = tile[i + n_slices];
-                        const float hq0 = fmaf(p0.x, ch, p0.y * sh);
-                        const float hq1 = fmaf(p1.x, ch, p1.y * sh);
+                // whole rounds of 2 * n_slices plans, then one round with the
+                // ragged tail (missing plans read as a plan at infinity)
+                auto sweep2 = [&](const float4 p0, const float4 p1) {
+                    const float hq0 = fmaf(p0.x, ch, p0.y * sh);
+                    const float hq1 = fmaf(p1.x, ch, p1.y * sh);
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) {
-                            const float u0 = fmaf(kv[v], hq0, p0.w);
-                            const float u1 = fmaf(kv[v], hq1, p1.w);
+                    for (int v = 0; v < NV; ++v) {
+                        const float u0 = fmaf(kv[v], hq0, p0.w);
+                        const float u1 = fmaf(kv[v], hq1, p1.w);
 #pragma unroll
-                            for (int c = 0; c < NC; ++c) {
-                                const float a0 = (c == ZC) ? u0 : fmaf(clf[c], p0.z, u0);
-                                const float a1 = (c == ZC) ? u1 : fmaf(clf[c], p1.z, u1);
-                                acc[c][v] = fminf(acc[c][v], fminf(a0, a1));
-                            }
+                        for (int c = 0; c < NC; ++c) {
+                            const float a0 = (c == ZC) ? u0 : fmaf(clf[c], p0.z, u0);
+                            const float a1 = (c == ZC) ? u1 : fmaf(clf[c], p1.z, u1);
+                            acc[c][v] = fminf(acc[c][v], fminf(a0, a1));
                         }
+                    }
+                };
+                const int full = (nv / (2 * n_slices)) * (2 * n_slices);
+                if (sweeper) {
+                    for (int i = my_slice; i < full; i += 2 * n_slices) sweep2(tile[i], tile[i + n_slices]);
+                    if (full < nv) {
+                        const float4 far = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                        const int i = full + my_slice;
+                        sweep2(i < nv ? tile[i] : far, i + n_slices < nv ? tile[i + n_slices] : far);
                     }
                 }
             }
@@ -670,9 +774,9 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 for (int q = 0; q < n_part; ++q) m = fminf(m, red[q * A + a]);
                 const int h = a / (NC * NV);
                 const double dx = sCos[h], dy = sSin[h];
-                const double step = cfg.speed[a % NV] * cfg.dt;
-                const double dz = cfg.climb[(a / NV) % NC] * cfg.dt;
-                const double d2 = nearest_d2<NC, NV>(cfg, a, m);
+                const double step = sStep[a % NV];
+                const double dz = sDz[(a / NV) % NC];
+                const double d2 = nearest_d2<NC, NV>(at, a, m);
                 sD2[a] = d2;
                 const double ox = step * dx, oy = step * dy;
                 float lo = -INFINITY, hi = -INFINITY;
@@ -712,7 +816,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             if (eval) {
                 for (int a = tid; a < A; a += NT) {
                     const int h = a / (NC * NV);
-                    const Scored r = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]);
+                    const Scored r = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]);
                     if (ev.V) ev.V[a] = r.V;
                     if (ev.G) ev.G[a] = r.G;
                     if (ev.I) ev.I[a] = r.I;
@@ -735,7 +839,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     double v = -INFINITY;
                     if (eval || sHi[a] >= cut) {
                         const int h = a / (NC * NV);
-                        v = score_action(cfg, tb, a, s, g, sCos[h], sSin[h], sD2[a]).V;
+                        v = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]).V;
                     }
                     sV[a] = v;
                     vm = fmax(vm, v);
@@ -771,8 +875,14 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             if (best < 0) {
                 st_status = FASTMDP_NO_VALID_ACTION;
             } else {
-                const int h = best / (NC * NV);
-                const Scored r = score_action(cfg, tb, best, s, g, sCos[h], sSin[h], sD2[best]);
+                Scored r;
+                if (cert) {                                // scored by the certificate
+                    r.x = st_r[0]; r.y = st_r[1]; r.z = st_r[2];
+                    r.V = st_r[3]; r.I = st_r[4]; r.clr = st_r[5];
+                } else {
+                    const int h = best / (NC * NV);
+                    r = score_action(cfg, tb, at, best, s, g, sCos[h], sSin[h], sD2[best]);
+                }
                 const size_t p = pt_base + n;
                 tr.xyz[p * 3 + 0] = r.x;
                 tr.xyz[p * 3 + 1] = r.y;
@@ -783,6 +893,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 tr.ep[p] = epoch;
                 tr.top[p] = top;
                 tr.col[p] = -1;
+                tr.nd[p] = sD2[best];
                 st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
                 st_n = n + 1;
                 if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
@@ -798,13 +909,29 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     // Commit validation of a finished OK trajectory against every table
     // entry it saw: each point as planned (FP64) must be at least R_sep from
     // every entry of its row that existed when the row was scored, and clear
-    // of the terrain.  Entries appended later are the sequencer's
-    // interaction check.
+    // of the terrain.  A point whose scored nearest-plan distance exceeds
+    // R_sep + 1 m cannot fail (the scored distance is within a small fraction
+    // of a millimetre of the exact one, and is exact near the well radius),
+    // so the exact check runs on the other points only, found in one
+    // parallel pass.  Entries appended later are the sequencer's interaction
+    // check.
     if (!eval && validate && st_status == FASTMDP_OK) {
         const int n = st_n;
         const double r2 = cfg.R_sep * cfg.R_sep;
+        const double clear2 = (cfg.R_sep + 1.0) * (cfg.R_sep + 1.0);
+        int *chk = reinterpret_cast<int *>(tile);         // the tile is free here; 4 * TILE >= max_steps + 1
+        if (tid == 0) st_flag = 0;
+        __syncthreads();
         int bad = 0;
-        for (int k = 0; k < n; ++k) {
+        for (int k = tid; k < n; k += NT) {
+            const double *x = tr.xyz + (pt_base + k) * 3;
+            if (tb.terr && x[2] - terrain_height(tb, x[0], x[1]) < 0.0) bad = 1;
+            if (!(tr.nd[pt_base + k] > clear2)) chk[atomicAdd(&st_flag, 1)] = k;
+        }
+        __syncthreads();
+        const int n_chk = st_flag;
+        for (int q = 0; q < n_chk; ++q) {
+            const int k = chk[q];
             const double *x = tr.xyz + (pt_base + k) * 3;
             const int lim = tr.seen[pt_base + k];
             const size_t rb = (size_t)(t0 + k) * tb.cap;
@@ -812,7 +939,6 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (entry_visible(tb, rb + j, seq) &&
                     entry_d2(x[0], x[1], x[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2)
                     bad = 1;
-            if (tb.terr && (k % NT) == tid && x[2] - terrain_height(tb, x[0], x[1]) < 0.0) bad = 1;
         }
         bad = __syncthreads_or(bad);
         if (tid == 0) S.valid = bad == 0;
@@ -842,7 +968,7 @@ static hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, co
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
                            t, s, list, tr, budget, validate, epoch, ev, prop);
     else
-        hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, true>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
+        hipLaunchKernelGGL((planner_kernel<kPropThreads, NC, NV, ZC, true>), dim3(nblk), dim3(kPropThreads), 0, st, c,
                            t, s, list, tr, budget, validate, epoch, ev, prop);
     return hipGetLastError();
 }

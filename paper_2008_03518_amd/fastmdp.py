@@ -102,7 +102,7 @@ def _load_lib():
     lib.fastmdp_mlp_train_step.argtypes = [P, I32, P, P, C.c_float, fp]
     lib.fastmdp_features.argtypes = [P, I32, P, P, P, P, P]
     lib.fastmdp_next_seq.argtypes = [P]
-    lib.fastmdp_set_proposal.argtypes = [P, I32, I32, P]
+    lib.fastmdp_set_proposal.argtypes = [P, I32, I32, I32, P]
     lib.fastmdp_eval_proposal.argtypes = [P, C.POINTER(_State), fp, fp, ip, ip, ip]
     lib.fastmdp_proposal_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64)]
     lib.fastmdp_device_alloc.argtypes = [I64, C.POINTER(P)]
@@ -431,8 +431,8 @@ class Context:
         _check("fastmdp_features", _lib.fastmdp_features(self._h, n, st.ptr, gl.ptr, rw.ptr, sq.ptr, out.ptr))
         return out
 
-    def set_proposal(self, mode: int, top_k: int = 8, net: "Optional[Mlp]" = None) -> None:
-        _check("fastmdp_set_proposal", _lib.fastmdp_set_proposal(self._h, int(mode), int(top_k),
+    def set_proposal(self, mode: int, top_k: int = 8, net: "Optional[Mlp]" = None, refresh: int = 1) -> None:
+        _check("fastmdp_set_proposal", _lib.fastmdp_set_proposal(self._h, int(mode), int(top_k), int(refresh),
                                                                  net._h if net is not None else None))
         self._net = net if mode == PROPOSE_MLP else None      # keep the network alive while selected
         self._top_k = int(top_k)
