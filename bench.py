@@ -61,10 +61,12 @@ def _leg(ctx, reqs, mode, net, k, steps, warmup, name, refresh=1):
     from paper_2008_03518_amd import fastmdp as fm
     ctx.set_proposal(mode, k, net, refresh)
 
+    bufs = [fm.Plan(ctx.capacity) for _ in range(reqs.n)]     # output buffers, reused by every pass
+
     def one():
         ctx.rewind()
         t = time.perf_counter()
-        plans, committed, done = ctx.plan_fcfs(reqs)
+        plans, committed, done = ctx.plan_fcfs(reqs, out=bufs)
         return time.perf_counter() - t, plans, committed, ctx.stats(), ctx.proposal_stats()
 
     for w in range(warmup):

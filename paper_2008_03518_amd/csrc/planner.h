@@ -75,7 +75,7 @@ struct Slot {
     int err;          // FCFS: table or log capacity exceeded
     int cert_hit;     // proposal steps certified, accumulated
     int cert_miss;    // proposal steps that fell back to the full sweep, accumulated
-    int pad;
+    int first;        // FCFS check: first affected point found so far (INT_MAX if none)
 };
 
 // Per-slot trajectory buffers, `stride` points per slot.  seen[k] is the

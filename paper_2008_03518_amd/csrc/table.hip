@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, 
                                                                    Traj tr) {
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
+    if (threadIdx.x == 0) S.first = 0x7fffffff;             // opened here for the checks that follow
     if (S.status != FASTMDP_OK || !S.valid) return;
     const int n = S.n_points, t0 = S.t0, own = S.seq;
     const size_t base = (size_t)slot * tr.stride;
@@ -154,9 +155,15 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, 
     if (err) S.err = 1;
 }
 
-__global__ __launch_bounds__(kPassThreads) void fcfs_check_kernel(DevCfg c, DevTable tb, Slot *slots,
-                                                                  const int *list, Traj tr, DeathLog dl,
-                                                                  int epoch) {
+// Check, part 1: withdrawn entries the request saw; the log range is split
+// over kDeadSplit workgroups per request (blockIdx.y), which fold their
+// finds into the request's first-affected-step minimum (Slot::first, opened
+// by the insert kernel).
+constexpr int kDeadSplit = 16;
+
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                       const int *list, Traj tr, DeathLog dl,
+                                                                       int epoch) {
     __shared__ int s_first, s_minep;
     const int tid = threadIdx.x;
     const int slot = list[blockIdx.x];
@@ -168,17 +175,55 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_kernel(DevCfg c, DevT
     int mine = 0x7fffffff;
     for (int k = tid; k < n; k += kPassThreads) mine = min(mine, tr.ep[base + k]);
     atomicMin(&s_minep, mine);
-    const double r2 = c.reach * c.reach;
+    __syncthreads();
+    const int minep = s_minep;
+    if (minep < epoch) {
+        const int lo = dl.start[minep + 1], hi = dl.start[epoch];
+        const double rs2 = c.reach_state * c.reach_state;
+        const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
+        for (int i = lo + blockIdx.y * kPassThreads + tid; i < hi; i += kPassThreads * kDeadSplit) {
+            const int row = dl.row[i], col = dl.col[i], e = dl.ep[i];
+            const int k = row - t0;
+            if (k < 0 || k >= n) continue;
+            if (col >= tr.seen[base + k] || e <= tr.ep[base + k]) continue;
+            const size_t idx = (size_t)row * tb.cap + col;
+            if (tb.own[idx] >= q) continue;
+            const double *sp = tr.xyz + (base + (k == 0 ? 0 : k - 1)) * 3;
+            if (entry_d2(sp[0], sp[1], sp[2], tb.X[idx], tb.Y[idx], tb.Z[idx]) < (k == 0 ? ro2 : rs2))
+                atomicMin(&s_first, k);
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && s_first != 0x7fffffff) atomicMin(&S.first, s_first);
+}
 
-    // added entries
-    for (int k = tid; k < n; k += kPassThreads) {
+// Check, part 2: added entries, kCheckPoints points of one request per
+// workgroup (blockIdx.y picks the points).  Each wave takes one point at a
+// time and its lanes read the row's new entries together; the wave stops at
+// the first entry in reach.
+constexpr int kCheckPoints = 64;
+
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                      const int *list, Traj tr) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    const int n = S.n_points, t0 = S.t0, q = S.seq;
+    const int k0 = blockIdx.y * kCheckPoints;
+    if (k0 >= n) return;
+    const size_t base = (size_t)slot * tr.stride;
+    const double r2 = c.reach * c.reach;
+    constexpr int per_wave = kCheckPoints / (kPassThreads / 64);
+    for (int i = 0; i < per_wave; ++i) {
+        const int k = k0 + wave * per_wave + i;             // wave-uniform
+        if (k >= n) break;
         const int row = t0 + k;
-        if (row >= tb.rows) continue;
+        if (row >= tb.rows) break;
         const int hi = min(tb.rowN[row], tb.cap);
         const int lo = tr.seen[base + k];
         if (lo >= hi) continue;
-        const double *x = tr.xyz + (base + k) * 3;     // chosen successor (the origin for k = 0)
-        double y[3] = {x[0], x[1], x[2]};              // largest action's successor, if different
+        const double *x = tr.xyz + (base + k) * 3;         // chosen successor (the origin for k = 0)
+        double y[3] = {x[0], x[1], x[2]};                  // largest action's successor, if different
         const int top = k > 0 ? tr.top[base + k] : -1;
         if (top >= 0) {
             const double *sp = tr.xyz + (base + k - 1) * 3;
@@ -196,38 +241,28 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_kernel(DevCfg c, DevT
             y[2] = sp[2] + c.climb[cl] * c.dt;
         }
         const size_t rb = (size_t)row * tb.cap;
-        for (int j = lo; j < hi; ++j) {
+        int hit = 0;
+        for (int j = lo + lane; j < hi && !hit; j += 64) {
             if (!entry_visible(tb, rb + j, q)) continue;
             const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
-            if (entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2) {
-                atomicMin(&s_first, k);
-                break;
-            }
+            hit = entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2;
+        }
+        if (__ballot(hit)) {
+            if (lane == 0) atomicMin(&S.first, k);
+            break;                                          // later points of this wave cannot be first
         }
     }
-    __syncthreads();
+}
 
-    // withdrawn entries
-    const int minep = s_minep;
-    if (minep < epoch) {
-        const int lo = dl.start[minep + 1], hi = dl.start[epoch];
-        const double rs2 = c.reach_state * c.reach_state;
-        const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
-        for (int i = lo + tid; i < hi; i += kPassThreads) {
-            const int row = dl.row[i], col = dl.col[i], e = dl.ep[i];
-            const int k = row - t0;
-            if (k < 0 || k >= n) continue;
-            if (col >= tr.seen[base + k] || e <= tr.ep[base + k]) continue;
-            const size_t idx = (size_t)row * tb.cap + col;
-            if (tb.own[idx] >= q) continue;
-            const double *sp = tr.xyz + (base + (k == 0 ? 0 : k - 1)) * 3;
-            if (entry_d2(sp[0], sp[1], sp[2], tb.X[idx], tb.Y[idx], tb.Z[idx]) < (k == 0 ? ro2 : rs2))
-                atomicMin(&s_first, k);
-        }
-    }
-    __syncthreads();
-    const int first = s_first;
-    // steps before the first affected one are consistent with the table now
+// Check, part 3 (one workgroup per request): steps before the first
+// affected one are consistent with the table now.
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_finish_kernel(DevTable tb, Slot *slots, const int *list,
+                                                                         Traj tr, int epoch) {
+    const int tid = threadIdx.x;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    const int n = S.n_points, t0 = S.t0, first = S.first;
+    const size_t base = (size_t)slot * tr.stride;
     for (int k = tid; k < min(n, first); k += kPassThreads) {
         const int row = t0 + k;
         if (row < tb.rows) tr.seen[base + k] = min(tb.rowN[row], tb.cap);
@@ -342,7 +377,11 @@ hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, con
                             const Traj &tr, const DeathLog &dl, int epoch, hipStream_t st) {
     if (n_list <= 0) return hipSuccess;
     hipLaunchKernelGGL(fcfs_insert_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr);
-    hipLaunchKernelGGL(fcfs_check_kernel, dim3(n_list), dim3(kPassThreads), 0, st, c, t, slots, list, tr, dl, epoch);
+    hipLaunchKernelGGL(fcfs_check_dead_kernel, dim3(n_list, kDeadSplit), dim3(kPassThreads), 0, st, c, t, slots, list,
+                       tr, dl, epoch);
+    hipLaunchKernelGGL(fcfs_check_add_kernel, dim3(n_list, (tr.stride + kCheckPoints - 1) / kCheckPoints),
+                       dim3(kPassThreads), 0, st, c, t, slots, list, tr);
+    hipLaunchKernelGGL(fcfs_check_finish_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr, epoch);
     hipLaunchKernelGGL(fcfs_withdraw_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr, dl, epoch);
     return hipGetLastError();
 }

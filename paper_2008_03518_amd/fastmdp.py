@@ -259,12 +259,13 @@ def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_lau
 
 
 class Plan:
-    """A trajectory returned by the planner (host arrays)."""
+    """A trajectory returned by the planner (host arrays; entries beyond
+    n_points are unspecified)."""
 
     def __init__(self, capacity: int):
-        self.xyz = np.zeros((capacity, 3))
-        self.action = np.zeros(capacity, dtype=np.int32)
-        self.value = np.zeros(capacity)
+        self.xyz = np.empty((capacity, 3))
+        self.action = np.empty(capacity, dtype=np.int32)
+        self.value = np.empty(capacity)
         self.c = _Plan(0, 0, 0, capacity, _dptr(self.xyz), _iptr(self.action), _dptr(self.value))
 
     @property
@@ -378,19 +379,23 @@ class Context:
         p.c.status, p.c.t0, p.c.n_points = OK, int(t0), xyz.shape[0]
         return self.commit_plan(p)
 
-    def plan_fcfs(self, requests, limit: Optional[int] = None, arrival_s=None):
+    def plan_fcfs(self, requests, limit: Optional[int] = None, arrival_s=None, out: Optional[list] = None):
         """Plan requests first-come-first-served with concurrent slots.
 
         With ``arrival_s`` (non-decreasing seconds), request i is admitted no
-        earlier than arrival_s[i] after the call starts.  Returns (plans,
-        committed, done_s): committed a bool array, done_s the acceptance time
-        of each request in seconds since the call started.
+        earlier than arrival_s[i] after the call starts.  ``out`` may supply
+        Plan buffers (of this context's capacity) to fill instead of new ones.
+        Returns (plans, committed, done_s): committed a bool array, done_s the
+        acceptance time of each request in seconds since the call started.
         """
         m = requests.n if limit is None else min(limit, requests.n)
         arr = (_Request * max(m, 1))()
         for k in range(m):
             arr[k] = _request(requests.origin[k], requests.goal[k], int(requests.t0[k]), int(requests.ident[k]))
-        plans = [Plan(self.capacity) for _ in range(m)]
+        if out is not None and len(out) >= m and all(p.c.capacity >= self.capacity for p in out[:m]):
+            plans = list(out[:m])
+        else:
+            plans = [Plan(self.capacity) for _ in range(m)]
         parr = (_Plan * max(m, 1))()
         for k in range(m):
             parr[k] = plans[k].c
