@@ -181,7 +181,9 @@ int fastmdp_num_plans(const fastmdp_ctx *ctx);
  * paper's "independent parallel instances" generalised to overlapping
  * requests).  Requests are admitted in order into up to max_slots slots --
  * request i not before arrival_s[i] seconds after the call starts (NULL: all
- * at once) -- and planned concurrently against the table as it stands.  Then,
+ * at once) -- and planned concurrently against the table as it stands, each
+ * planner launch taking the oldest unfinished requests, at most one per
+ * compute unit, and the finished ones entering the table tentatively.  Then,
  * strictly in request order, each finished trajectory is checked against
  * the plans committed after it scored their rows: if no committed point lies
  * within reach of a scored successor, the trajectory is the one a

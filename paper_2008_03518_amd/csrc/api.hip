@@ -561,10 +561,18 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
                 dirty = true;
             }
         if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
-        // plan every running slot for up to `budget` steps
+        // plan the oldest running requests, one per compute unit (the
+        // planner's workgroups take a CU each), for up to `budget` steps: a
+        // request that waits for the next launch plans against the plans its
+        // predecessors finish in this one instead of re-planning after them
         list.clear();
         for (int s = 0; s < S; ++s)
             if (slot_req[s] >= 0 && hs[s].status == fmdp::kRunning) list.push_back(s);
+        if ((int)list.size() > ctx->n_cu) {
+            std::nth_element(list.begin(), list.begin() + ctx->n_cu, list.end(),
+                             [&](int a, int b) { return hs[a].req < hs[b].req; });
+            list.resize(ctx->n_cu);
+        }
         if (list.empty() && next_commit == next_req) {
             // idle until the next arrival
             const double wait = arrival_s[next_req] - now_s();

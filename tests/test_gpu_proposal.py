@@ -306,6 +306,29 @@ def test_proposal_plans_identical_to_full_sweep(fm):
     net.close()
 
 
+@pytest.mark.parametrize("preset", ["small", "paper_scale"])
+def test_proposal_plans_identical_other_shapes(fm, preset):
+    """81 actions (9 x 3 x 3), with terrain for the paper-scale box: terrain
+    penalties enter the values and the bound alike."""
+    if preset == "small":
+        sc = S.small(seed=0, n_plans=200, n_requests=24)
+        sc.cfg.plan_capacity = 512                          # room for withdrawn tentative entries
+    else:
+        sc = S.paper_scale(seed=1, n_plans=2000, n_requests=24)
+    A = sc.cfg.n_actions
+    net = fm.Mlp(A)
+    net.set_params(_params(A, 60))
+    with fm.context_for(sc, max_slots=16) as ctx:
+        ctx.snapshot()
+        ref, com, st, _ = _run(ctx, sc.requests, fm.PROPOSE_NONE)
+        for name, mode, nt in (("goal", fm.PROPOSE_GOAL, None), ("untrained", fm.PROPOSE_MLP, net)):
+            plans, c2, st2, ps = _run(ctx, sc.requests, mode, nt, 8, 4)
+            _same_plans(plans, ref)
+            assert np.array_equal(c2, com)
+            _log(f"[identical {preset}] {name}: {ps['certified']}/{ps['certified'] + ps['fallbacks']} certified")
+    net.close()
+
+
 def test_training_gain_over_untrained(fm):
     from paper_2008_03518_amd import proposal as PR
     A = S.cfg_large_actions().n_actions
