@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--plans", type=int, default=3000)
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--slots", type=int, default=1024)
-    ap.add_argument("--steps-per-launch", type=int, default=256)
+    ap.add_argument("--steps-per-launch", type=int, default=512)
     ap.add_argument("--planner-threads", type=int, default=0, help="planning workgroup size: 0 or 1024")
     ap.add_argument("--top-k", type=int, default=8)
     ap.add_argument("--refresh", type=int, default=16, help="steps between re-rankings of the proposal")

@@ -86,8 +86,10 @@ typedef struct {
     int32_t plan_capacity;           /* known-plan entries per time row           */
     int32_t max_rows;                /* time rows in the table                    */
     int32_t max_slots;               /* requests planned concurrently (>= 1)      */
-    int32_t steps_per_launch;        /* FCFS engine: steps per slot between
-                                        acceptance passes (0: 256)                */
+    int32_t steps_per_launch;        /* FCFS engine: most steps per slot between
+                                        acceptance passes (0: 512); a launch also
+                                        ends once a quarter of its requests have
+                                        finished                                  */
     int32_t planner_threads;         /* planning workgroup size: 0 or 1024 (one
                                         request per compute unit)                 */
     double tie_rel;                  /* argmax: values within tie_rel*|max| of the

@@ -61,6 +61,7 @@ struct fastmdp_ctx {
     fmdp::PropArgs prop{};
     float *dEvF = nullptr;        // proposal eval outputs: features, logits
     int *dEvI = nullptr;          // top-k, certified, proposal's action
+    int *dStop = nullptr;         // finished-workgroup counter of a planner launch
     std::mutex mu;
     // counters of the last call
     long long st_pairs = 0, st_steps = 0, st_resumes = 0, st_launches = 0;
@@ -102,7 +103,7 @@ void free_all(fastmdp_ctx *c) {
     if (c->hSlots) hipHostFree(c->hSlots);
     if (c->hGather) hipHostFree(c->hGather);
     hipFree(c->dGather); hipFree(c->dList2); hipFree(c->dOff);
-    hipFree(c->dEvF); hipFree(c->dEvI);
+    hipFree(c->dEvF); hipFree(c->dEvI); hipFree(c->dStop);
     if (c->e0) hipEventDestroy(c->e0);
     if (c->e1) hipEventDestroy(c->e1);
     if (c->own) hipStreamDestroy(c->own);
@@ -169,11 +170,13 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
 }
 
 int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int validate, int epoch,
-                  const EvalOut &ev) {
+                  const EvalOut &ev, int stop_target = 0) {
     const int nt = fmdp::kPlanThreads;
     HIP_TRY(hipEventRecord(c->e0, c->stream));
+    const fmdp::LaunchStop stop{c->dStop, stop_target};
+    if (stop_target > 0) HIP_TRY(fmdp::launch_fill_int(c->dStop, 0, 1, c->stream));
     hipError_t e = fmdp::launch_planner(nblk, nt, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate,
-                                        epoch, ev, c->prop);
+                                        epoch, ev, c->prop, stop);
     if (e != hipSuccess) {
         std::fprintf(stderr, "libfastmdp: planner launch failed: %s\n", hipGetErrorString(e));
         return FASTMDP_E_DEVICE;
@@ -326,6 +329,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->dOff, (size_t)c->max_slots);
     rc = rc ? rc : dev_alloc(&c->dEvF, (size_t)FASTMDP_N_FEAT + fmdp::kMaxActions);
     rc = rc ? rc : dev_alloc(&c->dEvI, (size_t)FASTMDP_MAX_TOPK + 2);
+    rc = rc ? rc : dev_alloc(&c->dStop, (size_t)1);
     if (!rc && hipHostMalloc(reinterpret_cast<void **>(&c->hSlots), (size_t)c->max_slots * sizeof(Slot)) != hipSuccess)
         rc = FASTMDP_E_NOMEM;
     if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
@@ -526,7 +530,7 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
     const auto t_start = clk::now();
     auto now_s = [&]() { return std::chrono::duration<double>(clk::now() - t_start).count(); };
     const int S = std::min(ctx->max_slots, std::max(n, 1));
-    const int budget = ctx->cfg.steps_per_launch > 0 ? ctx->cfg.steps_per_launch : 256;
+    const int budget = ctx->cfg.steps_per_launch > 0 ? ctx->cfg.steps_per_launch : 512;
     const int seq0 = ctx->seq;
     Slot *hs = ctx->hSlots;                  // pinned mirror of the slots
     std::vector<int> slot_req(S, -1);        // request held by each slot
@@ -583,7 +587,11 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
             EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
-            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, epoch, none);
+            // the launch ends once a quarter of its requests have finished:
+            // the others resume after the acceptance pass, with new requests
+            // in the freed compute units
+            const int stop_target = std::max(1, (int)list.size() / 4);
+            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, epoch, none, stop_target);
             if (rc) return finish(rc);
             HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -144,11 +144,19 @@ __device__ __forceinline__ double entry_d2(double x, double y, double z, float p
     return dx * dx + dy * dy + dz * dz;
 }
 
+// Early end of a launch: every workgroup whose request finishes adds one to
+// *ctr; once it reaches target the others stop at their next step (they stay
+// resumable).  target 0: run the full budget.
+struct LaunchStop {
+    int *ctr;
+    int target;
+};
+
 // nt: workgroup size; kPlanThreads is the one built.  prop.mode selects the
 // proposal path (FASTMDP_PROPOSE_NONE: full sweep only).
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
                           const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
-                          const PropArgs &prop);
+                          const PropArgs &prop, const LaunchStop &stop);
 bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
 
 // features.hip: proposal features of n states (device arrays, see

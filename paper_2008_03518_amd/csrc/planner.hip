@@ -143,7 +143,7 @@ struct PlanGeom {
 template <int NT, int NC, int NV, int ZC, bool PROP>
 __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list,
                                                      Traj tr, int budget, int validate, int epoch, EvalOut ev,
-                                                     PropArgs prop) {
+                                                     PropArgs prop, LaunchStop stop) {
     using Geo = PlanGeom<NT>;
     constexpr int NW = Geo::NW, TILE = Geo::TILE, PRE = Geo::PRE;
     constexpr int KMAX = FASTMDP_MAX_TOPK, HID = FASTMDP_MLP_HIDDEN;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ double sCos[kMaxHeads], sSin[kMaxHeads];  // heading directions of the current step
     __shared__ unsigned sBand[kMaxActions / 32];
     __shared__ double st_s[3];
-    __shared__ int st_n, st_status, st_flag;
+    __shared__ int st_n, st_status, st_flag, st_stop;
     __shared__ double red_d[NW];
     __shared__ int s_wsum[NW];
     __shared__ int s_any;
@@ -216,6 +216,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         st_n = n;
         st_status = kRunning;
         st_flag = 0;
+        st_stop = 0;
         s_any = 0;
     }
     __syncthreads();
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (tid == 0) st_status = FASTMDP_TIMEOUT;
                 break;
             }
-            if (steps_here >= budget) break;               // resumable: stays running
+            if (steps_here >= budget || st_stop) break;    // resumable: stays running
         }
 
         // 1. heading directions: the goal bearing rotated by each offset
@@ -400,6 +401,10 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         const int n_next = eval ? 0 : row_count(row + 1);   // used after staging: latency hidden
         const bool single = n_row <= tcap;
 
+        // early end of the launch: read here, where the staging that follows
+        // waits for this step's loads anyway; acted on at the next step
+        if (stop.target > 0 && tid == 0 && !eval)
+            st_stop = __hip_atomic_load(stop.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= stop.target;
         int n_vis = 0;
         bool staged = false;
         int cert = 0;
@@ -560,28 +565,44 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                         kclf = sClf[c];
                         kzc = c == ZC;
                     }
+                    // the thread's staged plans in registers (slots past the
+                    // row's visible plans skipped), all K minima, then the K
+                    // wave reductions side by side
                     float4 pe[PRE];
 #pragma unroll
                     for (int i = 0; i < PRE; ++i) {
                         const int j = tid + i * NT;
                         pe[i] = j < n_vis ? tile[j] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
                     }
-                    for (int r = 0; r < K; ++r) {
-                        const float ch = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kch), r));
-                        const float sh = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ksh), r));
-                        const float kvv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kkv), r));
-                        const float clv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kclf), r));
-                        const int zc = __builtin_amdgcn_readlane(kzc, r);
-                        float m = INFINITY;
+                    const int n_pre = min(PRE, (n_vis + NT - 1) / NT);   // uniform
+                    float mk[KMAX];
 #pragma unroll
-                        for (int i = 0; i < PRE; ++i) {
-                            const float hq = fmaf(pe[i].x, ch, pe[i].y * sh);
-                            const float u = fmaf(kvv, hq, pe[i].w);
-                            const float d = zc ? u : fmaf(clv, pe[i].z, u);
-                            m = fminf(m, d);
+                    for (int r = 0; r < KMAX; ++r) {
+                        float m = INFINITY;
+                        if (r < K) {                                     // uniform
+                            const float ch = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kch), r));
+                            const float sh = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ksh), r));
+                            const float kvv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kkv), r));
+                            const float clv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kclf), r));
+                            const int zc = __builtin_amdgcn_readlane(kzc, r);
+#pragma unroll
+                            for (int i = 0; i < PRE; ++i) {
+                                if (i < n_pre) {                         // uniform
+                                    const float hq = fmaf(pe[i].x, ch, pe[i].y * sh);
+                                    const float u = fmaf(kvv, hq, pe[i].w);
+                                    const float d = zc ? u : fmaf(clv, pe[i].z, u);
+                                    m = fminf(m, d);
+                                }
+                            }
                         }
-                        m = wave_min_f32(m);
-                        if (lane == 0) sKm[wave][r] = m;
+                        mk[r] = m;
+                    }
+#pragma unroll
+                    for (int r = 0; r < KMAX; ++r) {
+                        if (r < K) {
+                            const float m = wave_min_f32(mk[r]);
+                            if (lane == 0) sKm[wave][r] = m;
+                        }
                     }
                 }
                 for (int w = tid; w < kMaxActions / 32; w += NT) sBand[w] = 0u;
@@ -947,6 +968,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     if (tid == 0 && !eval) {
         S.n_points = st_n;
         S.status = st_status;
+        if (stop.target > 0 && st_status != kRunning) atomicAdd(stop.ctr, 1);
     }
     if (tid == 0) {
         S.pairs += pairs;
@@ -962,24 +984,24 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
 template <int NC, int NV, int ZC>
 static hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
                            const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
-                           const PropArgs &prop) {
+                           const PropArgs &prop, const LaunchStop &stop) {
     (void)nt;
     if (prop.mode == FASTMDP_PROPOSE_NONE)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
-                           t, s, list, tr, budget, validate, epoch, ev, prop);
+                           t, s, list, tr, budget, validate, epoch, ev, prop, stop);
     else
         hipLaunchKernelGGL((planner_kernel<kPropThreads, NC, NV, ZC, true>), dim3(nblk), dim3(kPropThreads), 0, st, c,
-                           t, s, list, tr, budget, validate, epoch, ev, prop);
+                           t, s, list, tr, budget, validate, epoch, ev, prop, stop);
     return hipGetLastError();
 }
 
 #define FMDP_SHAPE(NC, NV, ZC) \
     if (c.n_climb == NC && c.n_speed == NV && zc == ZC) \
-        return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, ev, prop);
+        return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
 
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
                           const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
-                          const PropArgs &prop) {
+                          const PropArgs &prop, const LaunchStop &stop) {
     const int zc = c.zero_climb;
     if (prop.mode != FASTMDP_PROPOSE_NONE && (prop.k < 1 || prop.k > FASTMDP_MAX_TOPK || prop.k > c.n_actions))
         return hipErrorInvalidValue;
