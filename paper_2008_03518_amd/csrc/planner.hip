@@ -170,7 +170,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ int sK[KMAX];                                     // proposed actions, best first
     __shared__ float sKm[NW][KMAX];                              // per-wave nearest minima
     __shared__ int st_cert, st_best, st_top;
-    __shared__ double st_r[6];                                   // certified choice: x, y, z, V, I, clearance
+    __shared__ double st_r[6];                                   // chosen action's scoring: x, y, z, V, I, clearance
+    __shared__ int st_rok;                                       // st_r holds this step's choice (full sweep)
     __shared__ double sStep[FASTMDP_MAX_ACT_DIM], sDz[FASTMDP_MAX_ACT_DIM];   // speed*dt, climb*dt
     __shared__ float sKv[FASTMDP_MAX_ACT_DIM], sClf[FASTMDP_MAX_ACT_DIM];      // FP32 sweep constants
     const ActTab at{sStep, sDz};
@@ -668,6 +669,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     }
                     if (lane == 0) {
                         st_cert = ok;
+                        st_rok = 0;
                         st_best = best;
                         st_top = vb < vm ? top1 : -1;
                         pairs += (long long)(K + (rank && prop.mode == FASTMDP_PROPOSE_MLP ? 1 : 0)) * n_vis;
@@ -849,41 +851,67 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             }
 
             // 5. argmax (one wave: largest value, then the lowest index inside
-            //    the tie band)
+            //    the tie band).  The screening candidates are compacted with
+            //    ballots so that each lane values at most one per round in
+            //    FP64 (typically a single round); the advance reuses the
+            //    chosen action's scoring when it was done in the first round.
             if (wave == 0) {
                 float lb = -INFINITY;
                 for (int a = lane; a < A; a += 64) lb = fmaxf(lb, sLo[a]);
                 lb = wave_maxf(lb);
                 const float cut = lb - 1e-6f * fabsf(lb);
+                int *cand = reinterpret_cast<int *>(tile);    // the tile is free again here
+                int n_cand = 0;
+                for (int a0 = 0; a0 < A; a0 += 64) {
+                    const int a = a0 + lane;
+                    const bool c = a < A && (eval || sHi[a] >= cut);
+                    const uint64_t bal = __ballot(c);
+                    if (c)
+                        cand[n_cand + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0))] = a;
+                    n_cand += __popcll(bal);
+                }
                 double vm = -INFINITY;
-                for (int a = lane; a < A; a += 64) {
-                    double v = -INFINITY;
-                    if (eval || sHi[a] >= cut) {
+                Scored sc{};
+                int mine = 0x7fffffff;                         // this lane's first-round candidate
+                for (int c0 = 0; c0 < n_cand; c0 += 64) {
+                    const int ci = c0 + lane;
+                    if (ci < n_cand) {
+                        const int a = cand[ci];
                         const int h = a / (NC * NV);
-                        v = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]).V;
+                        const Scored r = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]);
+                        sV[a] = r.V;
+                        vm = fmax(vm, r.V);
+                        if (c0 == 0) {
+                            sc = r;
+                            mine = a;
+                        }
                     }
-                    sV[a] = v;
-                    vm = fmax(vm, v);
                 }
                 vm = wave_max(vm);
                 const double thr = vm - cfg.tie_rel * fabs(vm);
-                int li = 0x7fffffff;
-                for (int a = lane; a < A; a += 64)
-                    if (sV[a] >= thr) { li = a; break; }
+                int li = 0x7fffffff, ti = 0x7fffffff;
+                for (int ci = lane; ci < n_cand; ci += 64) {
+                    const int a = cand[ci];
+                    const double v = sV[a];
+                    if (v >= thr) li = min(li, a);
+                    if (v == vm) ti = min(ti, a);
+                }
                 li = wave_min(li);
+                ti = wave_min(ti);
                 const int best = vm == -INFINITY ? -1 : li;
                 // inside the tie band the chosen action may not be the largest:
                 // remember the (lowest-index) largest for the acceptance check
-                int top = -1;
-                if (best >= 0 && sV[best] < vm) {
-                    int ti = 0x7fffffff;
-                    for (int a = lane; a < A; a += 64)
-                        if (sV[a] == vm) { ti = a; break; }
-                    top = wave_min(ti);
+                const int top = (best >= 0 && sV[best] < vm) ? ti : -1;
+                const int reuse = __ballot(mine == best && best >= 0) != 0;
+                if (mine == best && best >= 0) {
+                    st_r[0] = sc.x; st_r[1] = sc.y; st_r[2] = sc.z;
+                    st_r[3] = sc.V; st_r[4] = sc.I; st_r[5] = sc.clr;
                 }
                 if (lane == 0) {
                     st_best = best;
                     st_top = top;
+                    st_rok = reuse;
                     pairs += (long long)A * n_vis;             // pairs with the plans this request sees
                     if (eval && ev.best) *ev.best = best;
                 }
@@ -897,7 +925,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 st_status = FASTMDP_NO_VALID_ACTION;
             } else {
                 Scored r;
-                if (cert) {                                // scored by the certificate
+                if (cert || st_rok) {                      // scored by the certificate or the argmax
                     r.x = st_r[0]; r.y = st_r[1]; r.z = st_r[2];
                     r.V = st_r[3]; r.I = st_r[4]; r.clr = st_r[5];
                 } else {
