@@ -159,6 +159,8 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.zeta_scale = (float)(-2.0 * c.dt);
     d.tie_rel = c.tie_rel;
     d.reach = std::max(c.R_intr, c.R_sep) + 1.0;
+    d.band_lo2 = std::max(c.R_intr - fmdp::kBand, 0.0) * std::max(c.R_intr - fmdp::kBand, 0.0);
+    d.band_hi2 = (c.R_intr + fmdp::kBand) * (c.R_intr + fmdp::kBand);
     double cmax = 0.0;
     for (int k = 0; k < c.n_climb; ++k) cmax = std::max(cmax, std::fabs(c.climb[k]));
     d.reach_state = d.reach + std::sqrt(vmax * vmax + cmax * cmax) * c.dt;

@@ -35,6 +35,7 @@ struct DevCfg {
     double tie_rel;
     double reach;                        // max(R_intr, R_sep) + 1 m: a plan farther than this from
                                          // a successor cannot change its value
+    double band_lo2, band_hi2;           // (R_intr -+ kBand)^2: squared distances recomputed exactly
     double reach_state;                  // reach + longest action step: a plan farther than this
                                          // from a state cannot change any of its successors' values
     int n_head, n_climb, n_speed, n_actions;

@@ -615,7 +615,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     for (int w = 0; w < NW; ++w) m = fminf(m, sKm[w][lane]);
                     const double d2 = nearest_d2<NC, NV>(at, a, m);
                     sD2[a] = d2;
-                    if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) {
+                    if (d2 > cfg.band_lo2 && d2 < cfg.band_hi2) {
                         atomicOr(&sBand[a >> 5], 1u << (a & 31));
                         band = 1;
                     }
@@ -821,7 +821,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     lo = V - e;
                     hi = V + e;
                 }
-                if (fabs(sqrt(fmax(d2, 0.0)) - cfg.R_intr) < kBand) {
+                if (d2 > cfg.band_lo2 && d2 < cfg.band_hi2) {
                     atomicOr(&sBand[a >> 5], 1u << (a & 31));
                     band = 1;
                     lo = -INFINITY;                            // valued in FP64 after the exact distance
