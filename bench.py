@@ -31,6 +31,22 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared distance
 
+# HBM bytes per planner launch on this workload, from the FETCH_SIZE /
+# WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
+# copy of known size), valid only for the kernel sources they were taken on.
+TRAFFIC_SOURCES = ("planner.hip", "planner.h", "proposal.h", "wave.h")
+TRAFFIC_SHA256 = "e8dffae782e0f9bb8e92af48ebf0a558062f6666f2ae14a7193e05cca8ad3947"
+TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 7.41e8, "full_sweep": 3.62e8}
+
+
+def _traffic(leg: str):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2008_03518_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES_PER_LAUNCH[leg] if h.hexdigest() == TRAFFIC_SHA256 else None
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -91,7 +107,7 @@ def _leg(ctx, reqs, mode, net, k, steps, warmup, name, refresh=1):
     return r
 
 
-def _roofline(r):
+def _roofline(r, leg):
     achieved = FLOPS_PER_PAIR * r["pairs"] / (r["kms"] * 1e-3) / 1e12
     return {
         "bound": "alu",
@@ -99,7 +115,8 @@ def _roofline(r):
         "peak": FP32_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-        "traffic": None,
+        "traffic": _traffic(leg),
+        "traffic_unit": "HBM bytes per launch",
         "kernel": "planner_kernel",
         "avg_launch_ms": r["kms"] / max(r["launches"], 1),
         "flops_per_launch": FLOPS_PER_PAIR * r["pairs"] / max(r["launches"], 1),
@@ -218,11 +235,11 @@ def main():
         "resumes": prop["resumes"],
         "committed_per_step": int(prop["committed"].sum()),
         "status_counts": {S.STATUS_NAMES[int(k)]: int((status == k).sum()) for k in np.unique(status)},
-        "roofline": _roofline(prop),
+        "roofline": _roofline(prop, "proposal"),
         "full_sweep": {
             "value": full["value"], "ms_per_step": full["ms_per_step"], "planner_steps": full["steps"],
             "pair_evals_per_s": full["pairs"] / (full["kms"] * 1e-3), "resumes": full["resumes"],
-            "roofline": _roofline(full),
+            "roofline": _roofline(full, "full_sweep"),
         },
         "training": train_info,
     }
