@@ -172,6 +172,12 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ int st_cert, st_best, st_top;
     __shared__ double st_r[6];                                   // chosen action's scoring: x, y, z, V, I, clearance
     __shared__ int st_rok;                                       // st_r holds this step's choice (full sweep)
+    // the last point taken, written to the trajectory after the next step's
+    // staging (its stores then overlap that step instead of holding up the
+    // wait for the row): x, y, z, value, nearest distance; index, action,
+    // row entries seen, epoch, top action
+    __shared__ double st_pv[5];
+    __shared__ int st_pi[5], st_pend;
     __shared__ double sStep[FASTMDP_MAX_ACT_DIM], sDz[FASTMDP_MAX_ACT_DIM];   // speed*dt, climb*dt
     __shared__ float sKv[FASTMDP_MAX_ACT_DIM], sClf[FASTMDP_MAX_ACT_DIM];      // FP32 sweep constants
     const ActTab at{sStep, sDz};
@@ -218,6 +224,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         st_status = kRunning;
         st_flag = 0;
         st_stop = 0;
+        st_pend = 0;
         s_any = 0;
     }
     __syncthreads();
@@ -358,6 +365,22 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         if (pre_n > 0) load_chunk(row, 0);
     }
 
+    auto flush_point = [&]() {                                  // thread 0
+        if (!st_pend) return;
+        const size_t p = pt_base + st_pi[0];
+        tr.xyz[p * 3 + 0] = st_pv[0];
+        tr.xyz[p * 3 + 1] = st_pv[1];
+        tr.xyz[p * 3 + 2] = st_pv[2];
+        tr.val[p] = st_pv[3];
+        tr.nd[p] = st_pv[4];
+        tr.act[p] = st_pi[1];
+        tr.seen[p] = st_pi[2];
+        tr.ep[p] = st_pi[3];
+        tr.top[p] = st_pi[4];
+        tr.col[p] = -1;
+        st_pend = 0;
+    };
+
     long long pairs = 0;
     int steps_here = 0, hits = 0, misses = 0;
     int since = 1 << 30;                                         // steps since the last ranking
@@ -450,6 +473,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (rank)
                     for (int w = tid; w < kMaxActions / 32; w += NT) sInK[w] = 0u;
                 lds_barrier();                             // tile staged, headings visible
+                if (tid == 0) flush_point();
                 if (rank && prop.mode == FASTMDP_PROPOSE_MLP) {
                     const float ux = (float)cb, uy = (float)sb;
                     for (int j = tid; j < n_vis; j += NT) {
@@ -731,6 +755,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     }
                     n_vis += nv;
                     lds_barrier();
+                    if (base == 0 && tid == 0) flush_point();
                 }
                 if (base == 0 && sweeper) {
                     ch = (float)sCos[my_h];
@@ -932,17 +957,11 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     const int h = best / (NC * NV);
                     r = score_action(cfg, tb, at, best, s, g, sCos[h], sSin[h], sD2[best]);
                 }
-                const size_t p = pt_base + n;
-                tr.xyz[p * 3 + 0] = r.x;
-                tr.xyz[p * 3 + 1] = r.y;
-                tr.xyz[p * 3 + 2] = r.z;
-                tr.act[p] = best;
-                tr.val[p] = r.V;
-                tr.seen[p] = n_row;
-                tr.ep[p] = epoch;
-                tr.top[p] = top;
-                tr.col[p] = -1;
-                tr.nd[p] = sD2[best];
+                flush_point();                             // a point still pending (row without plans)
+                st_pv[0] = r.x; st_pv[1] = r.y; st_pv[2] = r.z;
+                st_pv[3] = r.V; st_pv[4] = sD2[best];
+                st_pi[0] = n; st_pi[1] = best; st_pi[2] = n_row; st_pi[3] = epoch; st_pi[4] = top;
+                st_pend = 1;
                 st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
                 st_n = n + 1;
                 if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
@@ -953,7 +972,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         lds_barrier();
         if (eval) break;
     }
-    __syncthreads();   // st_status written by thread 0 on the way out of the loop
+    if (tid == 0) flush_point();
+    __syncthreads();   // st_status written by thread 0 on the way out of the loop; trajectory complete
 
     // Commit validation of a finished OK trajectory against every table
     // entry it saw: each point as planned (FP64) must be at least R_sep from
