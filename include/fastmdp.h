@@ -83,7 +83,8 @@ typedef struct {
     double speed[FASTMDP_MAX_ACT_DIM];   /* [m/s], n_speed used, all > 0          */
     int32_t max_steps;               /* steps per request (<= max_steps+1 points),
                                         at most 16383                             */
-    int32_t plan_capacity;           /* known-plan entries per time row           */
+    int32_t plan_capacity;           /* known-plan entries per time row, a
+                                        multiple of 4                            */
     int32_t max_rows;                /* time rows in the table                    */
     int32_t max_slots;               /* requests planned concurrently (>= 1)      */
     int32_t steps_per_launch;        /* FCFS engine: most steps per slot between

@@ -120,7 +120,9 @@ int check_cfg(const fastmdp_config *c) {
         return FASTMDP_E_INVAL;
     for (int v = 0; v < c->n_speed; ++v)
         if (!(c->speed[v] > 0.0)) return FASTMDP_E_INVAL;
-    if (c->max_steps < 1 || c->max_steps + 1 > fmdp::kMaxPoints || c->plan_capacity < 1 || c->max_rows < 2)
+    if (c->max_steps < 1 || c->max_steps + 1 > fmdp::kMaxPoints || c->max_rows < 2) return FASTMDP_E_INVAL;
+    // rows are read four entries (16 bytes) per lane
+    if (c->plan_capacity < 4 || c->plan_capacity % 4 != 0)
         return FASTMDP_E_INVAL;
     if (!(c->tie_rel >= 0.0)) return FASTMDP_E_INVAL;
     if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads) return FASTMDP_E_INVAL;

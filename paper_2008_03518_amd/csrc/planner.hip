@@ -129,6 +129,16 @@ __device__ __forceinline__ int wave_min(int v) { return wave_min_i32(v); }
 // for exponents up to 40 (over 50 km at 20 m per step), and the result a
 // relative error below 1e-5; 1e-4 leaves a factor of ten.
 constexpr float kGoalBoundRel = 1e-4f;
+constexpr int kCachePolicyDevice = 16;    // cache-policy bits of a device-coherent load (sc1)
+
+// 16 bytes per lane from global memory straight into LDS (lane l's bytes
+// land at lds + 16 l).  The host pass never sees the gfx950 form of the
+// builtin: it rejects it, silently dropping every kernel that uses it.
+__device__ __forceinline__ void load_lds16(const void *g, void *lds) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0);
+#endif
+}
 
 // Longest run of steps the proposal sits out after repeated fallbacks.
 constexpr int kMaxBackoff = 16;
@@ -138,6 +148,8 @@ struct PlanGeom {
     static constexpr int NW = NT / 64;
     static constexpr int TILE = 4096;                        // row entries per chunk (LDS tile)
     static constexpr int PRE = TILE / NT;                    // chunk entries per thread
+    static constexpr int PRE4 = TILE / (4 * NT);             // 16-byte (four-entry) groups per thread
+    static_assert(TILE % (4 * NT) == 0, "a chunk is a whole number of four-entry groups per thread");
 };
 
 template <int NT, int NC, int NV, int ZC, bool PROP>
@@ -145,11 +157,12 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                                                      Traj tr, int budget, int validate, int epoch, EvalOut ev,
                                                      PropArgs prop, LaunchStop stop) {
     using Geo = PlanGeom<NT>;
-    constexpr int NW = Geo::NW, TILE = Geo::TILE, PRE = Geo::PRE;
+    constexpr int NW = Geo::NW, TILE = Geo::TILE, PRE = Geo::PRE, PRE4 = Geo::PRE4;
     constexpr int KMAX = FASTMDP_MAX_TOPK, HID = FASTMDP_MLP_HIDDEN;
     __shared__ float4 tile[TILE];               // staged plans; reused for the slice partial minima
-    __shared__ float rawX[TILE], rawY[TILE], rawZ[TILE];   // the next row chunk as read from the table
-    __shared__ int rawK[TILE];                             // its visibility keys
+    // the next row chunk as read from the table, and its visibility keys
+    __shared__ __attribute__((aligned(16))) float rawX[TILE], rawY[TILE], rawZ[TILE];
+    __shared__ __attribute__((aligned(16))) int rawK[TILE];
     __shared__ double sV[kMaxActions];          // FP64 values of the candidate actions
     __shared__ double sD2[kMaxActions];         // squared nearest-plan distance per action
     __shared__ float sLo[kMaxActions], sHi[kMaxActions];   // FP32 value brackets
@@ -157,7 +170,10 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ double sCos[kMaxHeads], sSin[kMaxHeads];  // heading directions of the current step
     __shared__ unsigned sBand[kMaxActions / 32];
     __shared__ double st_s[3];
-    __shared__ int st_n, st_status, st_flag, st_stop;
+    __shared__ int st_n, st_status, st_flag;
+    __shared__ int st_stop[2];                  // early end: read at the top of local step i from slot i & 1
+    __shared__ int sNextN[2];                   // entry count of row r + 1, slot (r + 1) & 1, loaded with row r
+    __shared__ int sStopV;                      // launch stop counter as last read
     __shared__ double red_d[NW];
     __shared__ int s_wsum[NW];
     __shared__ int s_any;
@@ -213,6 +229,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     }
     if constexpr (PROP) feat_reset(sFa, tid);
     if (tid == 0) {
+        sStopV = 0;
         const int n = eval ? 0 : S.n_points;
         if (n == 0) {
             st_s[0] = S.origin[0]; st_s[1] = S.origin[1]; st_s[2] = S.origin[2];
@@ -223,7 +240,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         st_n = n;
         st_status = kRunning;
         st_flag = 0;
-        st_stop = 0;
+        st_stop[0] = st_stop[1] = 0;
         st_pend = 0;
         s_any = 0;
     }
@@ -261,31 +278,42 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     }
 
     // One chunk of a row (up to tcap entries) travels from the table to LDS
-    // without registers (global_load_lds): entry base + j, j = i*NT +
-    // wave*64 + lane, lands at raw*[j].  Each wave later stages exactly the
-    // entries its own loads brought (thread tid takes j = tid + i*NT), so it
-    // only waits for its own loads (vmcnt), with no barrier, and may issue
-    // the next row's loads as soon as it has staged this one.  The first
-    // chunk of the next step's row is in flight during the sweep.
+    // without registers (global_load_lds): entry base + j lands at raw*[j].
+    // Each lane later stages exactly the entries its own loads brought, so a
+    // wave only waits for its own loads (vmcnt), with no barrier, and may
+    // issue the next row's loads as soon as it has staged this one.  The
+    // first chunk of the next step's row is in flight during the sweep.
     int pre_n = 0, pre_lim = 0;
     auto load_chunk = [&](int row, int base) {
         const size_t rb = (size_t)row * tb.cap + base;
         const int lim = min(pre_n - base, tcap);
         pre_lim = lim;
-        // the per-lane offset is made opaque so that the addresses are formed
-        // here (one add each) instead of being hoisted out of the step loop,
-        // where they would occupy 32 registers and be spilled
-        int ofs = tid;
+        // the entry count of the following row travels with the first chunk,
+        // so that the step does not wait for it on its own
+        if (base == 0 && tid == 0) {
+            if (row + 1 < tb.rows)
+                __builtin_amdgcn_global_load_lds(tb.rowN + row + 1, sNextN + ((row + 1) & 1), 4, 0, 0);
+            else
+                sNextN[(row + 1) & 1] = 0;
+        }
+        // 16 bytes (four entries) per lane and instruction: lane l of wave w
+        // brings entries j0 + 4l .. j0 + 4l + 3, j0 = i*4*NT + 256w.  A group
+        // that runs past the row's count stays inside the row's capacity (a
+        // multiple of four), so the read is in bounds; the extra entries are
+        // never staged.  The per-lane offset is made opaque so that the
+        // addresses are formed here instead of being hoisted out of the step
+        // loop, where they would occupy registers and be spilled.
+        int ofs = 4 * tid;
         asm volatile("" : "+v"(ofs));
 #pragma unroll
-        for (int i = 0; i < PRE; ++i) {
-            const int j0 = i * NT + wave * 64;             // wave-uniform LDS destination
-            const int j = ofs + i * NT;
+        for (int i = 0; i < PRE4; ++i) {
+            const int j0 = i * 4 * NT + wave * 256;        // wave-uniform LDS destination
+            const int j = ofs + i * 4 * NT;
             if (j < lim) {
-                __builtin_amdgcn_global_load_lds(tb.X + rb + j, rawX + j0, 4, 0, 0);
-                __builtin_amdgcn_global_load_lds(tb.Y + rb + j, rawY + j0, 4, 0, 0);
-                __builtin_amdgcn_global_load_lds(tb.Z + rb + j, rawZ + j0, 4, 0, 0);
-                __builtin_amdgcn_global_load_lds(tb.vis + rb + j, rawK + j0, 4, 0, 0);
+                load_lds16(tb.X + rb + j, rawX + j0);
+                load_lds16(tb.Y + rb + j, rawY + j0);
+                load_lds16(tb.Z + rb + j, rawZ + j0);
+                load_lds16(tb.vis + rb + j, rawK + j0);
             }
         }
     };
@@ -293,19 +321,37 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     // Stage the chunk into the tile, compacted to the entries this request
     // sees, as (q_x, q_y, -2 dt q_z, |q|^2) with q = p - s.  Returns the
     // count.
+    int steps_here = 0;
+    // Early end of the launch (thread 0): the flag for the next step from
+    // the counter value read during the previous step, then the next read,
+    // device-coherent and straight into LDS, so that nothing waits for it
+    // until the next step's staging
+    auto take_stop = [&]() {
+        if (tid == 0 && stop.target > 0 && !eval) {
+            st_stop[(steps_here + 1) & 1] = sStopV >= stop.target;
+            __builtin_amdgcn_global_load_lds(stop.ctr, &sStopV, 4, 0, kCachePolicyDevice);
+        }
+    };
     auto stage_chunk = [&](const double s[3]) -> int {
         // wave-level compaction with ballots: entry i of this lane goes after
         // the wave's visible entries of lower i and of lower lanes at i
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of the chunk landed
-        bool pv[PRE];
-        uint64_t bal[PRE];
+        take_stop();
+        // each lane stages the four-entry groups its own loads brought
+        bool pv[PRE4][4];
+        uint64_t bal[PRE4][4];
         int wcnt = 0;
 #pragma unroll
-        for (int i = 0; i < PRE; ++i) {
-            const int j = tid + i * NT;
-            pv[i] = j < pre_lim && rawK[j] < seq;
-            bal[i] = __ballot(pv[i]);
-            wcnt += __popcll(bal[i]);
+        for (int i = 0; i < PRE4; ++i) {
+            const int j = 4 * tid + i * 4 * NT;
+            const int4 k4 = *reinterpret_cast<const int4 *>(rawK + j);
+            const int kv4[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                pv[i][m] = j + m < pre_lim && kv4[m] < seq;
+                bal[i][m] = __ballot(pv[i][m]);
+                wcnt += __popcll(bal[i][m]);
+            }
         }
         if (lane == 0) s_wsum[wave] = wcnt;
         lds_barrier();
@@ -317,17 +363,27 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             total += t;
         }
 #pragma unroll
-        for (int i = 0; i < PRE; ++i) {
-            if (pv[i]) {
-                const int j = tid + i * NT;
-                const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[i] >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal[i], 0));
-                const float qx = (float)((double)rawX[j] - s[0]);
-                const float qy = (float)((double)rawY[j] - s[1]);
-                const float qz = (float)((double)rawZ[j] - s[2]);
-                tile[pos + below] = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+        for (int i = 0; i < PRE4; ++i) {
+            const int j = 4 * tid + i * 4 * NT;
+            const float4 x4 = *reinterpret_cast<const float4 *>(rawX + j);
+            const float4 y4 = *reinterpret_cast<const float4 *>(rawY + j);
+            const float4 z4 = *reinterpret_cast<const float4 *>(rawZ + j);
+            const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+            const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
+            const float zs[4] = {z4.x, z4.y, z4.z, z4.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (pv[i][m]) {
+                    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[i][m] >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal[i][m], 0));
+                    const float qx = (float)((double)xs[m] - s[0]);
+                    const float qy = (float)((double)ys[m] - s[1]);
+                    const float qz = (float)((double)zs[m] - s[2]);
+                    tile[pos + below] =
+                        make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+                }
+                pos += __popcll(bal[i][m]);
             }
-            pos += __popcll(bal[i]);
         }
         return total;
     };
@@ -382,7 +438,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     };
 
     long long pairs = 0;
-    int steps_here = 0, hits = 0, misses = 0;
+    int hits = 0, misses = 0;
     int since = 1 << 30;                                         // steps since the last ranking
     // after a step that fell back, the proposal sits out `skip` steps (the
     // full sweep runs directly), doubling up to kMaxBackoff while it keeps
@@ -408,7 +464,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (tid == 0) st_status = FASTMDP_TIMEOUT;
                 break;
             }
-            if (steps_here >= budget || st_stop) break;    // resumable: stays running
+            if (steps_here >= budget || st_stop[steps_here & 1]) break;   // resumable: stays running
         }
 
         // 1. heading directions: the goal bearing rotated by each offset
@@ -422,13 +478,14 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         const int row = t + 1;
         const int n_row = pre_n;
         const size_t rb = (size_t)row * tb.cap;
-        const int n_next = eval ? 0 : row_count(row + 1);   // used after staging: latency hidden
         const bool single = n_row <= tcap;
+        // entry count of the next row: it came with this row's first chunk
+        // (read after that chunk's staging), else it is read directly
+        auto next_count = [&]() -> int {
+            if (eval) return 0;
+            return n_row > 0 ? min(sNextN[(row + 1) & 1], tb.cap) : row_count(row + 1);
+        };
 
-        // early end of the launch: read here, where the staging that follows
-        // waits for this step's loads anyway; acted on at the next step
-        if (stop.target > 0 && tid == 0 && !eval)
-            st_stop = __hip_atomic_load(stop.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= stop.target;
         int n_vis = 0;
         bool staged = false;
         int cert = 0;
@@ -439,7 +496,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             if (prop.mode != FASTMDP_PROPOSE_NONE && single && (skip == 0 || eval)) {
                 if (n_row > 0) n_vis = stage_chunk(s);
                 if (!eval) {                               // next row in flight meanwhile
-                    pre_n = n_next;
+                    pre_n = next_count();
                     if (pre_n > 0) load_chunk(row + 1, 0);
                 }
                 staged = true;
@@ -666,8 +723,13 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     const double vm = wave_max(v);
                     const double thr = vm - cfg.tie_rel * fabs(vm);
                     float tau = -INFINITY;
-                    for (int b = lane; b < A; b += 64)
-                        if (!(sInK[b >> 5] >> (b & 31) & 1u)) tau = fmaxf(tau, sGu[b]);
+#pragma unroll
+                    for (int j = 0; j < kMaxActions / 64; ++j) {   // every read issued at once
+                        const int b = j * 64 + lane;               // below kMaxActions: in bounds
+                        const float gu = sGu[b];
+                        const unsigned inK = sInK[b >> 5] >> (b & 31) & 1u;
+                        if (b < A && !inK) tau = fmaxf(tau, gu);
+                    }
                     tau = wave_maxf(tau);
                     int ok = vm > -INFINITY && (double)tau < thr;
                     // the FP32 bound is loose by up to 1e-4: where it does not
@@ -750,7 +812,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     }
                     nv = stage_chunk(s);
                     if (base == 0 && single && !eval) {    // next row in flight during the sweep
-                        pre_n = n_next;
+                        pre_n = next_count();
                         if (pre_n > 0) load_chunk(row + 1, 0);
                     }
                     n_vis += nv;
@@ -790,7 +852,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             }
             lds_barrier();                                   // tile is reused below
             if (n_row == 0 && !eval && !staged) {
-                pre_n = n_next;
+                pre_n = next_count();
                 if (pre_n > 0) load_chunk(row + 1, 0);
             }
 
@@ -818,8 +880,26 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             const float gx32 = (float)(g[0] - s[0]), gy32 = (float)(g[1] - s[1]), gz32 = (float)(g[2] - s[2]);
             int band = 0;
             for (int a = tid; a < A; a += NT) {
-                float m = INFINITY;
-                for (int q = 0; q < n_part; ++q) m = fminf(m, red[q * A + a]);
+                // eight independent chains, so that eight LDS reads are in
+                // flight instead of one
+                float m8[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) m8[j] = INFINITY;
+                int q = 0;
+                for (; q + 8 <= n_part; q += 8) {
+                    float r8[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) r8[j] = red[(q + j) * A + a];
+                    // all eight values live at once: the reads are issued
+                    // back to back rather than each after the previous one
+                    asm volatile("" ::"v"(r8[0]), "v"(r8[1]), "v"(r8[2]), "v"(r8[3]), "v"(r8[4]), "v"(r8[5]),
+                                 "v"(r8[6]), "v"(r8[7]));
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) m8[j] = fminf(m8[j], r8[j]);
+                }
+                for (; q < n_part; ++q) m8[0] = fminf(m8[0], red[q * A + a]);
+                const float m = fminf(fminf(fminf(m8[0], m8[1]), fminf(m8[2], m8[3])),
+                                      fminf(fminf(m8[4], m8[5]), fminf(m8[6], m8[7])));
                 const int h = a / (NC * NV);
                 const double dx = sCos[h], dy = sSin[h];
                 const double step = sStep[a % NV];
@@ -871,7 +951,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     if (ev.T) ev.T[a] = r.T;
                 }
             } else if (!single) {
-                pre_n = n_next;                                // in flight during the argmax and advance
+                pre_n = next_count();                                // in flight during the argmax and advance
                 if (pre_n > 0) load_chunk(row + 1, 0);
             }
 
@@ -881,15 +961,25 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             //    FP64 (typically a single round); the advance reuses the
             //    chosen action's scoring when it was done in the first round.
             if (wave == 0) {
+                constexpr int kGroups = kMaxActions / 64;
+                float lo_r[kGroups], hi_r[kGroups];          // every bracket read at once
+#pragma unroll
+                for (int j = 0; j < kGroups; ++j) {
+                    const int a = j * 64 + lane;               // below kMaxActions: in bounds
+                    lo_r[j] = a < A ? sLo[a] : -INFINITY;
+                    hi_r[j] = a < A ? sHi[a] : -INFINITY;
+                }
                 float lb = -INFINITY;
-                for (int a = lane; a < A; a += 64) lb = fmaxf(lb, sLo[a]);
+#pragma unroll
+                for (int j = 0; j < kGroups; ++j) lb = fmaxf(lb, lo_r[j]);
                 lb = wave_maxf(lb);
                 const float cut = lb - 1e-6f * fabsf(lb);
                 int *cand = reinterpret_cast<int *>(tile);    // the tile is free again here
                 int n_cand = 0;
-                for (int a0 = 0; a0 < A; a0 += 64) {
-                    const int a = a0 + lane;
-                    const bool c = a < A && (eval || sHi[a] >= cut);
+#pragma unroll
+                for (int j = 0; j < kGroups; ++j) {
+                    const int a = j * 64 + lane;
+                    const bool c = a < A && (eval || hi_r[j] >= cut);
                     const uint64_t bal = __ballot(c);
                     if (c)
                         cand[n_cand + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
@@ -957,6 +1047,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     const int h = best / (NC * NV);
                     r = score_action(cfg, tb, at, best, s, g, sCos[h], sSin[h], sD2[best]);
                 }
+                if (n_row == 0) take_stop();               // no staging in this step
                 flush_point();                             // a point still pending (row without plans)
                 st_pv[0] = r.x; st_pv[1] = r.y; st_pv[2] = r.z;
                 st_pv[3] = r.V; st_pv[4] = sD2[best];

@@ -271,7 +271,7 @@ def small(seed: int = 0, n_plans: int = 50, n_requests: int = 1) -> Scenario:
 def paper_scale(seed: int = 1, n_plans: int = 2000, n_requests: int = 200) -> Scenario:
     """2000 known plans, 256 x 256 terrain of 50 hills, 200 FCFS requests (seed 1)."""
     cfg = cfg_paper_scale()
-    cfg.plan_capacity = max(cfg.plan_capacity, n_plans + n_requests + 64)
+    cfg.plan_capacity = max(cfg.plan_capacity, (n_plans + n_requests + 64 + 3) // 4 * 4)
     rng = np.random.default_rng(seed)
     terrain = make_terrain(rng, cfg)
     plans = make_known_plans(rng, cfg, n_plans, terrain)
@@ -282,7 +282,7 @@ def paper_scale(seed: int = 1, n_plans: int = 2000, n_requests: int = 200) -> Sc
 def large_actions(seed: int = 2, n_plans: int = 3000, n_requests: int = 1000) -> Scenario:
     """3000 known plans, 360 actions, dt 0.5 s, 1000 FCFS requests (seed 2)."""
     cfg = cfg_large_actions()
-    cfg.plan_capacity = max(cfg.plan_capacity, n_plans + n_requests + 64)
+    cfg.plan_capacity = max(cfg.plan_capacity, (n_plans + n_requests + 64 + 3) // 4 * 4)
     rng = np.random.default_rng(seed)
     plans = make_known_plans(rng, cfg, n_plans)
     req = make_requests(rng, cfg, n_requests, plans)
