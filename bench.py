@@ -35,8 +35,8 @@ FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared dist
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "planner.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "e8dffae782e0f9bb8e92af48ebf0a558062f6666f2ae14a7193e05cca8ad3947"
-TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 7.41e8, "full_sweep": 3.62e8}
+TRAFFIC_SHA256 = "c9a249fbe7473e995ef18189a439c186bf85c06bc2c16e4c9f54dfd0cf65c892"
+TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 7.65e8, "full_sweep": 3.73e8}
 
 
 def _traffic(leg: str):
@@ -123,6 +123,20 @@ def _roofline(r, leg):
     }
 
 
+def _calibrate_copy():
+    """A copy of known size for scaling the FETCH_SIZE / WRITE_SIZE counters
+    to bytes: 65536 rows of 4096 B gathered by an int64 index, three times
+    (256 MiB read plus the 512 KiB index, 256 MiB written, per dispatch)."""
+    from paper_2008_03518_amd import fastmdp as fm
+    n, row = 65536, 4096
+    src = fm.DeviceArray((n, row // 4), np.float32)
+    idx = fm.DeviceArray.from_host(np.arange(n, dtype=np.int64))
+    for _ in range(3):
+        src.gather(idx).free()
+    print(json.dumps({"calibration_copy": {"dispatches": 3, "read_bytes": n * row + n * 8,
+                                           "written_bytes": n * row}}), flush=True)
+
+
 def _same_plans(a, b) -> bool:
     for p, q in zip(a, b):
         n = p.n_points
@@ -155,11 +169,16 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work; 0 disables")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the copy of known size that scales the HBM byte counters, then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.calibrate_copy:
+        _calibrate_copy()
+        return
 
     from paper_2008_03518_amd import fastmdp as fm
     from paper_2008_03518_amd import proposal as PR
