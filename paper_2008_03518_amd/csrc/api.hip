@@ -147,11 +147,8 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.abs_r_intr = std::fabs(c.r_intr);
     d.abs_r_terr = std::fabs(c.r_terr);
     d.log2_gamma_f = (float)std::log2(c.gamma);
-    d.log2_gamma_intr_f = (float)std::log2(c.gamma_intr);
     d.inv_ell_f = (float)(1.0 / d.ell);
     d.abs_r_goal_f = (float)d.abs_r_goal;
-    d.abs_r_intr_f = (float)d.abs_r_intr;
-    d.R_intr2_f = (float)(c.R_intr * c.R_intr);
     for (int k = 0; k < FASTMDP_MAX_ACT_DIM; ++k) {
         d.climb[k] = c.climb[k];
         d.speed[k] = c.speed[k];

@@ -26,8 +26,7 @@ struct DevCfg {
     double gamma, r_goal, r_intr, R_intr, gamma_intr, R_sep, r_terr, R_terr, gamma_terr;
     double log_gamma, log_gamma_intr, log_gamma_terr;   // discounts as exp(log_gamma * distance/ell)
     double abs_r_goal, abs_r_intr, abs_r_terr;
-    float log2_gamma_f, log2_gamma_intr_f, inv_ell_f;   // FP32 screening of the values
-    float abs_r_goal_f, abs_r_intr_f, R_intr2_f;
+    float log2_gamma_f, inv_ell_f, abs_r_goal_f;        // FP32 goal-term bound of the proposal
     double climb[FASTMDP_MAX_ACT_DIM], speed[FASTMDP_MAX_ACT_DIM];
     float kv[FASTMDP_MAX_ACT_DIM];       // -2 * speed * dt
     float climb_f[FASTMDP_MAX_ACT_DIM];  // climb rates

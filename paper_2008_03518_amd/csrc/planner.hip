@@ -163,9 +163,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     // the next row chunk as read from the table, and its visibility keys
     __shared__ __attribute__((aligned(16))) float rawX[TILE], rawY[TILE], rawZ[TILE];
     __shared__ __attribute__((aligned(16))) int rawK[TILE];
-    __shared__ double sV[kMaxActions];          // FP64 values of the candidate actions
     __shared__ double sD2[kMaxActions];         // squared nearest-plan distance per action
-    __shared__ float sLo[kMaxActions], sHi[kMaxActions];   // FP32 value brackets
     __shared__ double sC0[kMaxHeads], sS0[kMaxHeads];    // cos, sin of the heading offsets 2*pi*h/H
     __shared__ double sCos[kMaxHeads], sSin[kMaxHeads];  // heading directions of the current step
     __shared__ unsigned sBand[kMaxActions / 32];
@@ -176,6 +174,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ int sStopV;                      // launch stop counter as last read
     __shared__ double red_d[NW];
     __shared__ int s_wsum[NW];
+    __shared__ int s_wli[NW], s_wti[NW];        // per-wave argmax partials
     __shared__ int s_any;
     // proposal path only
     __shared__ FeatAcc sFa;                                      // traffic feature accumulators
@@ -187,7 +186,6 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ float sKm[NW][KMAX];                              // per-wave nearest minima
     __shared__ int st_cert, st_best, st_top;
     __shared__ double st_r[6];                                   // chosen action's scoring: x, y, z, V, I, clearance
-    __shared__ int st_rok;                                       // st_r holds this step's choice (full sweep)
     // the last point taken, written to the trajectory after the next step's
     // staging (its stores then overlap that step instead of holding up the
     // wait for the row): x, y, z, value, nearest distance; index, action,
@@ -755,7 +753,6 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     }
                     if (lane == 0) {
                         st_cert = ok;
-                        st_rok = 0;
                         st_best = best;
                         st_top = vb < vm ? top1 : -1;
                         pairs += (long long)(K + (rank && prop.mode == FASTMDP_PROPOSE_MLP ? 1 : 0)) * n_vis;
@@ -785,6 +782,20 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (tid == 0) ++misses;                    // backing off, or a row larger than one tile
             }
         }
+
+        // the step's point and state from the chosen action's scoring (one
+        // thread); a point still pending (row without plans) is written first
+        auto advance = [&](const Scored &r, int best, int top) {
+            flush_point();
+            st_pv[0] = r.x; st_pv[1] = r.y; st_pv[2] = r.z;
+            st_pv[3] = r.V; st_pv[4] = sD2[best];
+            st_pi[0] = n; st_pi[1] = best; st_pi[2] = n_row; st_pi[3] = epoch; st_pi[4] = top;
+            st_pend = 1;
+            st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
+            st_n = n + 1;
+            if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
+            else if (r.clr < 0.0) st_status = FASTMDP_REJECT_TERRAIN;
+        };
 
         if (!cert) {
             // 2-3. stage (compacted) and sweep the row chunk by chunk: every
@@ -867,19 +878,18 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             for (int w = tid; w < kMaxActions / 32; w += NT) sBand[w] = 0u;
             lds_barrier();
 
-            // 4. per-action value, screened in FP32.  The nearest-plan squared
-            //    distance is m + |Delta|^2 with m from the FP32 sweep.  Each
-            //    action gets an FP32 bracket [lo, hi] of its value (1e-4 of the
-            //    terms it combines, far above the FP32 error); only actions whose
-            //    bracket reaches the largest lower bound can be chosen (or tie with
-            //    the choice) and are valued again in FP64 below.  Actions whose
-            //    nearest distance lands within kBand of the well radius get their
-            //    distance recomputed exactly in FP64 and are always valued in FP64,
-            //    so that well membership is decided in FP64.  The box and the
-            //    terrain clearance are decided in FP64.
-            const float gx32 = (float)(g[0] - s[0]), gy32 = (float)(g[1] - s[1]), gz32 = (float)(g[2] - s[2]);
-            int band = 0;
-            for (int a = tid; a < A; a += NT) {
+            // 4. per-action value, one action per thread, in FP64 (the
+            //    scoring the oracle does): the nearest-plan squared distance is
+            //    m + |Delta|^2 with m from the FP32 sweep.  Actions whose
+            //    nearest distance lands within kBand of the well radius get it
+            //    recomputed exactly in FP64 first, so that well membership is
+            //    decided in FP64.  The chosen action's scoring stays in its
+            //    thread's registers for the advance.
+            const int a = tid;                                   // A <= kMaxActions <= NT
+            Scored myr{};
+            double myV = -INFINITY;
+            bool myband = false;
+            if (a < A) {
                 // eight independent chains, so that eight LDS reads are in
                 // flight instead of one
                 float m8[8];
@@ -900,163 +910,104 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 for (; q < n_part; ++q) m8[0] = fminf(m8[0], red[q * A + a]);
                 const float m = fminf(fminf(fminf(m8[0], m8[1]), fminf(m8[2], m8[3])),
                                       fminf(fminf(m8[4], m8[5]), fminf(m8[6], m8[7])));
-                const int h = a / (NC * NV);
-                const double dx = sCos[h], dy = sSin[h];
-                const double step = sStep[a % NV];
-                const double dz = sDz[(a / NV) % NC];
                 const double d2 = nearest_d2<NC, NV>(at, a, m);
                 sD2[a] = d2;
-                const double ox = step * dx, oy = step * dy;
-                float lo = -INFINITY, hi = -INFINITY;
-                if (!outside_box(cfg, s[0] + ox, s[1] + oy, s[2] + dz)) {
-                    const float ex = gx32 - (float)ox, ey = gy32 - (float)oy, ez = gz32 - (float)dz;
-                    const float G = cfg.abs_r_goal_f *
-                                    exp2f(cfg.log2_gamma_f * (sqrtf(ex * ex + ey * ey + ez * ez) * cfg.inv_ell_f));
-                    const float d2f = (float)d2;
-                    float pen = 0.0f;
-                    if (d2f < cfg.R_intr2_f)
-                        pen = cfg.abs_r_intr_f * exp2f(cfg.log2_gamma_intr_f * (sqrtf(fmaxf(d2f, 0.0f)) * cfg.inv_ell_f));
-                    if (tb.terr) {
-                        const double clr = s[2] + dz - terrain_height(tb, s[0] + ox, s[1] + oy);
-                        if (clr < cfg.R_terr)
-                            pen = fmaxf(pen, (float)(cfg.abs_r_terr * exp(cfg.log_gamma_terr * (fmax(clr, 0.0) / cfg.ell))));
-                    }
-                    const float V = G - pen;
-                    const float e = 1e-4f * (G + pen) + 1e-30f;
-                    lo = V - e;
-                    hi = V + e;
-                }
                 if (d2 > cfg.band_lo2 && d2 < cfg.band_hi2) {
                     atomicOr(&sBand[a >> 5], 1u << (a & 31));
-                    band = 1;
-                    lo = -INFINITY;                            // valued in FP64 after the exact distance
-                    hi = INFINITY;
+                    myband = true;
+                } else {
+                    const int h = a / (NC * NV);
+                    myr = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], d2);
+                    myV = myr.V;
                 }
-                sLo[a] = lo;
-                sHi[a] = hi;
             }
-            if (band) s_any = 1;
+
+            // 5. argmax over the workgroup: the largest value vm, then the
+            //    lowest index inside the tie band [vm - tie |vm|, vm], and the
+            //    lowest-index largest action (kept when the choice is not the
+            //    largest, for the acceptance check); DPP wave reductions, one
+            //    partial per wave in LDS
+            double wv = wave_max(myV);
+            if (lane == 0) red_d[wave] = wv;
+            if (myband) s_any = 1;
             lds_barrier();
             const int any_band = s_any;
-            lds_barrier();
-            if (tid == 0) s_any = 0;                           // read by all before the reset
-            if (any_band) band_recheck(s, n_row, rb);          // uniform; almost never taken
-            if (eval) {
-                for (int a = tid; a < A; a += NT) {
+            if (any_band) {                                      // uniform; almost never taken
+                lds_barrier();                                   // every thread has read the flag
+                if (tid == 0) s_any = 0;
+                band_recheck(s, n_row, rb);
+                if (myband) {
                     const int h = a / (NC * NV);
-                    const Scored r = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]);
-                    if (ev.V) ev.V[a] = r.V;
-                    if (ev.G) ev.G[a] = r.G;
-                    if (ev.I) ev.I[a] = r.I;
-                    if (ev.T) ev.T[a] = r.T;
+                    myr = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]);
+                    myV = myr.V;
+                }
+                wv = wave_max(myV);
+                if (lane == 0) red_d[wave] = wv;
+                lds_barrier();
+            }
+            double vm = -INFINITY;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) vm = fmax(vm, red_d[w]);
+            const double thr = vm - cfg.tie_rel * fabs(vm);
+            const int li = wave_min(a < A && myV >= thr ? a : 0x7fffffff);
+            const int ti = wave_min(a < A && myV == vm ? a : 0x7fffffff);
+            if (lane == 0) {
+                s_wli[wave] = li;
+                s_wti[wave] = ti;
+            }
+            if (eval) {
+                if (a < A) {
+                    if (ev.V) ev.V[a] = myr.V;
+                    if (ev.G) ev.G[a] = myr.G;
+                    if (ev.I) ev.I[a] = myr.I;
+                    if (ev.T) ev.T[a] = myr.T;
                 }
             } else if (!single) {
-                pre_n = next_count();                                // in flight during the argmax and advance
+                pre_n = next_count();                            // in flight during the advance
                 if (pre_n > 0) load_chunk(row + 1, 0);
             }
-
-            // 5. argmax (one wave: largest value, then the lowest index inside
-            //    the tie band).  The screening candidates are compacted with
-            //    ballots so that each lane values at most one per round in
-            //    FP64 (typically a single round); the advance reuses the
-            //    chosen action's scoring when it was done in the first round.
-            if (wave == 0) {
-                constexpr int kGroups = kMaxActions / 64;
-                float lo_r[kGroups], hi_r[kGroups];          // every bracket read at once
+            lds_barrier();
+            int best = 0x7fffffff, top = 0x7fffffff;
 #pragma unroll
-                for (int j = 0; j < kGroups; ++j) {
-                    const int a = j * 64 + lane;               // below kMaxActions: in bounds
-                    lo_r[j] = a < A ? sLo[a] : -INFINITY;
-                    hi_r[j] = a < A ? sHi[a] : -INFINITY;
+            for (int w = 0; w < NW; ++w) {
+                best = min(best, s_wli[w]);
+                top = min(top, s_wti[w]);
+            }
+            if (vm == -INFINITY) best = -1;
+            if (tid == 0) {
+                pairs += (long long)A * n_vis;                   // pairs with the plans this request sees
+                if (eval && ev.best) *ev.best = best;
+                if (!eval && best < 0) st_status = FASTMDP_NO_VALID_ACTION;
+                if (!eval && n_row == 0) take_stop();            // no staging in this step
+            }
+            // top is kept when the choice is not the largest
+            if constexpr (!PROP) {
+                // 6. advance, by the chosen action's thread (its scoring is in
+                //    its registers)
+                if (!eval && best >= 0 && a == best) advance(myr, best, top != best ? top : -1);
+            } else {
+                // (with the proposal, thread 0 advances on every path: one
+                // copy of the advance keeps that variant's registers down)
+                if (best >= 0 && a == best) {
+                    st_r[0] = myr.x; st_r[1] = myr.y; st_r[2] = myr.z;
+                    st_r[3] = myr.V; st_r[4] = myr.I; st_r[5] = myr.clr;
                 }
-                float lb = -INFINITY;
-#pragma unroll
-                for (int j = 0; j < kGroups; ++j) lb = fmaxf(lb, lo_r[j]);
-                lb = wave_maxf(lb);
-                const float cut = lb - 1e-6f * fabsf(lb);
-                int *cand = reinterpret_cast<int *>(tile);    // the tile is free again here
-                int n_cand = 0;
-#pragma unroll
-                for (int j = 0; j < kGroups; ++j) {
-                    const int a = j * 64 + lane;
-                    const bool c = a < A && (eval || hi_r[j] >= cut);
-                    const uint64_t bal = __ballot(c);
-                    if (c)
-                        cand[n_cand + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0))] = a;
-                    n_cand += __popcll(bal);
-                }
-                double vm = -INFINITY;
-                Scored sc{};
-                int mine = 0x7fffffff;                         // this lane's first-round candidate
-                for (int c0 = 0; c0 < n_cand; c0 += 64) {
-                    const int ci = c0 + lane;
-                    if (ci < n_cand) {
-                        const int a = cand[ci];
-                        const int h = a / (NC * NV);
-                        const Scored r = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]);
-                        sV[a] = r.V;
-                        vm = fmax(vm, r.V);
-                        if (c0 == 0) {
-                            sc = r;
-                            mine = a;
-                        }
-                    }
-                }
-                vm = wave_max(vm);
-                const double thr = vm - cfg.tie_rel * fabs(vm);
-                int li = 0x7fffffff, ti = 0x7fffffff;
-                for (int ci = lane; ci < n_cand; ci += 64) {
-                    const int a = cand[ci];
-                    const double v = sV[a];
-                    if (v >= thr) li = min(li, a);
-                    if (v == vm) ti = min(ti, a);
-                }
-                li = wave_min(li);
-                ti = wave_min(ti);
-                const int best = vm == -INFINITY ? -1 : li;
-                // inside the tie band the chosen action may not be the largest:
-                // remember the (lowest-index) largest for the acceptance check
-                const int top = (best >= 0 && sV[best] < vm) ? ti : -1;
-                const int reuse = __ballot(mine == best && best >= 0) != 0;
-                if (mine == best && best >= 0) {
-                    st_r[0] = sc.x; st_r[1] = sc.y; st_r[2] = sc.z;
-                    st_r[3] = sc.V; st_r[4] = sc.I; st_r[5] = sc.clr;
-                }
-                if (lane == 0) {
+                if (tid == 0) {
                     st_best = best;
-                    st_top = top;
-                    st_rok = reuse;
-                    pairs += (long long)A * n_vis;             // pairs with the plans this request sees
-                    if (eval && ev.best) *ev.best = best;
+                    st_top = top != best ? top : -1;
                 }
+                lds_barrier();
             }
         }
-
-        // 6. advance (thread 0, which also wrote st_best and st_top)
-        if (tid == 0 && !eval) {
-            const int best = st_best, top = st_top;
-            if (best < 0) {
-                st_status = FASTMDP_NO_VALID_ACTION;
-            } else {
+        if constexpr (PROP) {
+            // 6. advance (thread 0), from the scoring the certificate or the
+            //    argmax left in st_r
+            if (tid == 0 && !eval && st_best >= 0) {
                 Scored r;
-                if (cert || st_rok) {                      // scored by the certificate or the argmax
-                    r.x = st_r[0]; r.y = st_r[1]; r.z = st_r[2];
-                    r.V = st_r[3]; r.I = st_r[4]; r.clr = st_r[5];
-                } else {
-                    const int h = best / (NC * NV);
-                    r = score_action(cfg, tb, at, best, s, g, sCos[h], sSin[h], sD2[best]);
-                }
-                if (n_row == 0) take_stop();               // no staging in this step
-                flush_point();                             // a point still pending (row without plans)
-                st_pv[0] = r.x; st_pv[1] = r.y; st_pv[2] = r.z;
-                st_pv[3] = r.V; st_pv[4] = sD2[best];
-                st_pi[0] = n; st_pi[1] = best; st_pi[2] = n_row; st_pi[3] = epoch; st_pi[4] = top;
-                st_pend = 1;
-                st_s[0] = r.x; st_s[1] = r.y; st_s[2] = r.z;
-                st_n = n + 1;
-                if (r.I > 0.0) st_status = FASTMDP_REJECT_SEPARATION;
-                else if (r.clr < 0.0) st_status = FASTMDP_REJECT_TERRAIN;
+                r.x = st_r[0]; r.y = st_r[1]; r.z = st_r[2];
+                r.V = st_r[3]; r.I = st_r[4]; r.clr = st_r[5];
+                if (cert && n_row == 0) take_stop();             // no staging in this step
+                advance(r, st_best, st_top);
             }
         }
         steps_here += 1;
