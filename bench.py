@@ -18,6 +18,7 @@ timed on a bounded sample of the same requests.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -35,8 +36,8 @@ FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared dist
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "planner.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "c9a249fbe7473e995ef18189a439c186bf85c06bc2c16e4c9f54dfd0cf65c892"
-TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 7.65e8, "full_sweep": 3.73e8}
+TRAFFIC_SHA256 = "4ff5f381df89ac25e7f7621f8c2593d8832ab6b637fe65edd5552266026476b6"
+TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 7.83e8, "full_sweep": 4.24e8}
 
 
 def _traffic(leg: str):
@@ -81,9 +82,15 @@ def _leg(ctx, reqs, mode, net, k, steps, warmup, name, refresh=1):
 
     def one():
         ctx.rewind()
-        t = time.perf_counter()
-        plans, committed, done = ctx.plan_fcfs(reqs, out=bufs)
-        return time.perf_counter() - t, plans, committed, ctx.stats(), ctx.proposal_stats()
+        gc.collect()                   # no Python collection inside the timed region
+        gc.disable()
+        try:
+            t = time.perf_counter()
+            plans, committed, done = ctx.plan_fcfs(reqs, out=bufs)
+            el = time.perf_counter() - t
+        finally:
+            gc.enable()
+        return el, plans, committed, ctx.stats(), ctx.proposal_stats()
 
     for w in range(warmup):
         el, *_ = one()
