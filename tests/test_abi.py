@@ -66,3 +66,28 @@ int main(void) {
     got = [ctypes.sizeof(fm._Config), ctypes.sizeof(fm._Request), ctypes.sizeof(fm._Plan),
            ctypes.sizeof(fm._State), fm._Config.tie_rel.offset]
     assert [int(x) for x in out] == got
+
+
+def test_create_rejects_invalid_configs():
+    """Configuration errors come back as E_INVAL before any device call."""
+    import copy
+    _lib_path()
+    from paper_2008_03518_amd import fastmdp as fm
+    from paper_2008_03518_amd import scenario as S
+    base = S.cfg_small()
+    out = ctypes.c_void_p()
+
+    def create(**changes):
+        cfg = copy.deepcopy(base)
+        for k, v in changes.items():
+            setattr(cfg, k, v)
+        c = fm.make_config(cfg)
+        return fm._lib.fastmdp_create(ctypes.byref(c), ctypes.byref(out))
+
+    assert create(plan_capacity=254) == fm.E_INVAL       # rows are read four entries per lane
+    assert create(plan_capacity=2) == fm.E_INVAL
+    assert create(gamma=1.0) == fm.E_INVAL
+    assert create(dt=0.0) == fm.E_INVAL
+    assert create(max_steps=16383 + 1) == fm.E_INVAL
+    assert create(max_rows=1) == fm.E_INVAL
+    assert fm._lib.fastmdp_create(None, ctypes.byref(out)) == fm.E_INVAL
