@@ -166,7 +166,8 @@ def main():
     ap.add_argument("--steps-per-launch", type=int, default=512)
     ap.add_argument("--planner-threads", type=int, default=0, help="planning workgroup size: 0 or 1024")
     ap.add_argument("--top-k", type=int, default=8)
-    ap.add_argument("--refresh", type=int, default=16, help="steps between re-rankings of the proposal")
+    ap.add_argument("--refresh", type=int, default=64,
+                    help="steps between re-rankings of the proposal (a fallback also re-ranks)")
     ap.add_argument("--train-tuples", type=int, default=1000000)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--params", default="", help="load trained proposal parameters (.npz) instead of training")
