@@ -176,6 +176,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     __shared__ int s_wsum[NW];
     __shared__ int s_wli[NW], s_wti[NW];        // per-wave argmax partials
     __shared__ int s_any;
+    __shared__ int s_nvis;                      // visible row entries counted by the DMA-buffer K sweep
     // proposal path only
     __shared__ FeatAcc sFa;                                      // traffic feature accumulators
     __shared__ __attribute__((aligned(16))) uint16_t sAct[3][HID];   // BF16 features, hidden 1, hidden 2
@@ -241,6 +242,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         st_stop[0] = st_stop[1] = 0;
         st_pend = 0;
         s_any = 0;
+        s_nvis = 0;
     }
     __syncthreads();
 
@@ -492,18 +494,26 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         // from them when the certificate holds.
         if constexpr (PROP) {
             if (prop.mode != FASTMDP_PROPOSE_NONE && single && (skip == 0 || eval)) {
-                if (n_row > 0) n_vis = stage_chunk(s);
-                if (!eval) {                               // next row in flight meanwhile
-                    pre_n = next_count();
-                    if (pre_n > 0) load_chunk(row + 1, 0);
-                }
-                staged = true;
-                const int K = min(prop.k, A);
-                if (n_row == 0) lds_barrier();             // headings visible (staging has its own barrier)
                 // the ranking (and the proposed set) is refreshed every
                 // prop.refresh steps and after every fallback; the certificate
                 // is decided at every step
                 const bool rank = eval || since >= prop.refresh;
+                // Unless the network's features need the staged tile, the K
+                // actions are swept straight from the row's DMA buffers, and
+                // the row is staged only if the step falls back to the full
+                // sweep (the buffers still hold it until the next row's loads
+                // are issued, after the certificate).
+                const bool fused = !eval && !(rank && prop.mode == FASTMDP_PROPOSE_MLP);
+                if (!fused) {
+                    if (n_row > 0) n_vis = stage_chunk(s);
+                    if (!eval) {                           // next row in flight meanwhile
+                        pre_n = next_count();
+                        if (pre_n > 0) load_chunk(row + 1, 0);
+                    }
+                    staged = true;
+                }
+                const int K = min(prop.k, A);
+                if (n_row == 0 || fused) lds_barrier();    // headings visible (staging has its own barrier)
                 // upper bound of every action's goal term (FP32 with a margin;
                 // -inf outside the box, decided in FP64)
                 {
@@ -528,7 +538,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (rank)
                     for (int w = tid; w < kMaxActions / 32; w += NT) sInK[w] = 0u;
                 lds_barrier();                             // tile staged, headings visible
-                if (tid == 0) flush_point();
+                if (tid == 0 && !fused) flush_point();
                 if (rank && prop.mode == FASTMDP_PROPOSE_MLP) {
                     const float ux = (float)cb, uy = (float)sb;
                     for (int j = tid; j < n_vis; j += NT) {
@@ -649,12 +659,51 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                     // row's visible plans skipped), all K minima, then the K
                     // wave reductions side by side
                     float4 pe[PRE];
+                    int n_pre;
+                    if (!fused) {
 #pragma unroll
-                    for (int i = 0; i < PRE; ++i) {
-                        const int j = tid + i * NT;
-                        pe[i] = j < n_vis ? tile[j] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                        for (int i = 0; i < PRE; ++i) {
+                            const int j = tid + i * NT;
+                            pe[i] = j < n_vis ? tile[j] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                        }
+                        n_pre = min(PRE, (n_vis + NT - 1) / NT);         // uniform
+                    } else {
+                        // this lane's four-entry groups as its loads brought
+                        // them, in the staging's arithmetic; entries the
+                        // request does not see and slots past the row read as
+                        // a plan at infinity
+                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                        take_stop();
+                        const int lim = n_row > 0 ? pre_lim : 0;
+                        int seen_w = 0;
+#pragma unroll
+                        for (int gi = 0; gi < PRE4; ++gi) {
+                            const int j = 4 * tid + gi * 4 * NT;
+                            const int4 k4 = *reinterpret_cast<const int4 *>(rawK + j);
+                            const float4 x4 = *reinterpret_cast<const float4 *>(rawX + j);
+                            const float4 y4 = *reinterpret_cast<const float4 *>(rawY + j);
+                            const float4 z4 = *reinterpret_cast<const float4 *>(rawZ + j);
+                            const int kv4[4] = {k4.x, k4.y, k4.z, k4.w};
+                            const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+                            const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
+                            const float zs[4] = {z4.x, z4.y, z4.z, z4.w};
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) {
+                                const bool vis = j + m < lim && kv4[m] < seq;
+                                float4 p = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                                if (vis) {
+                                    const float qx = (float)((double)xs[m] - s[0]);
+                                    const float qy = (float)((double)ys[m] - s[1]);
+                                    const float qz = (float)((double)zs[m] - s[2]);
+                                    p = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+                                }
+                                pe[gi * 4 + m] = p;
+                                seen_w += __popcll(__ballot(vis));
+                            }
+                        }
+                        if (lane == 0) atomicAdd(&s_nvis, seen_w);
+                        n_pre = min(PRE, 4 * ((lim + 4 * NT - 1) / (4 * NT)));   // uniform
                     }
-                    const int n_pre = min(PRE, (n_vis + NT - 1) / NT);   // uniform
                     float mk[KMAX];
 #pragma unroll
                     for (int r = 0; r < KMAX; ++r) {
@@ -687,6 +736,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 }
                 for (int w = tid; w < kMaxActions / 32; w += NT) sBand[w] = 0u;
                 lds_barrier();
+                if (fused) n_vis = s_nvis;                     // reset by thread 0 two barriers on
                 int band = 0;
                 if (wave == 0 && lane < K) {
                     const int a = sK[lane];
@@ -703,7 +753,10 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 lds_barrier();
                 const int any_band = s_any;
                 lds_barrier();
-                if (tid == 0) s_any = 0;
+                if (tid == 0) {
+                    s_any = 0;
+                    s_nvis = 0;
+                }
                 if (any_band) band_recheck(s, n_row, rb);
                 // certificate: the best exact value among the K, less the tie
                 // band, must exceed an upper bound of every other action's
@@ -764,6 +817,15 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 }
                 lds_barrier();
                 cert = eval ? 0 : st_cert;                 // eval always runs the full sweep too
+                if (fused) {
+                    // a fallback needs the staged tile: the row is still in the
+                    // DMA buffers; then the next row's loads
+                    if (!cert && n_row > 0) n_vis = stage_chunk(s);
+                    staged = !cert;
+                    pre_n = next_count();
+                    if (pre_n > 0) load_chunk(row + 1, 0);
+                    if (tid == 0) flush_point();
+                }
                 if (!eval) {
                     if (cert) {
                         backoff = 1;
