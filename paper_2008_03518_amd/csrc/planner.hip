@@ -644,8 +644,9 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 // the result does not depend on the order).  Lane r holds the
                 // constants of action r; each round broadcasts them.
                 {
+                    // (the zero climb's constant is 0, so fmaf(0, z, u) = u: the
+                    // full sweep's skipped term)
                     float kch = 0.0f, ksh = 0.0f, kkv = 0.0f, kclf = 0.0f;
-                    int kzc = 0;
                     if (lane < K) {
                         const int a = sK[lane];
                         const int h = a / (NC * NV), c = (a / NV) % NC, v = a % NV;
@@ -653,7 +654,6 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                         ksh = (float)sSin[h];
                         kkv = sKv[v];
                         kclf = sClf[c];
-                        kzc = c == ZC;
                     }
                     // the thread's staged plans in registers (slots past the
                     // row's visible plans skipped), all K minima, then the K
@@ -713,24 +713,25 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                             const float sh = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ksh), r));
                             const float kvv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kkv), r));
                             const float clv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kclf), r));
-                            const int zc = __builtin_amdgcn_readlane(kzc, r);
 #pragma unroll
                             for (int i = 0; i < PRE; ++i) {
                                 if (i < n_pre) {                         // uniform
                                     const float hq = fmaf(pe[i].x, ch, pe[i].y * sh);
                                     const float u = fmaf(kvv, hq, pe[i].w);
-                                    const float d = zc ? u : fmaf(clv, pe[i].z, u);
-                                    m = fminf(m, d);
+                                    m = fminf(m, fmaf(clv, pe[i].z, u));
                                 }
                             }
                         }
                         mk[r] = m;
                     }
+                    // the K wave minima, eight at a time
+                    static_assert(KMAX % 8 == 0, "minima are reduced in groups of eight");
 #pragma unroll
-                    for (int r = 0; r < KMAX; ++r) {
-                        if (r < K) {
-                            const float m = wave_min_f32(mk[r]);
-                            if (lane == 0) sKm[wave][r] = m;
+                    for (int r0 = 0; r0 < KMAX; r0 += 8) {
+                        if (r0 < K) {                                    // uniform
+                            const float m = wave_min8_f32(mk + r0, lane);
+                            const int r = r0 + 2 * (lane >> 4) + ((lane >> 3) & 1);
+                            if ((lane & 7) == 0 && r < K) sKm[wave][r] = m;
                         }
                     }
                 }

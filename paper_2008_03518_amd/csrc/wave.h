@@ -96,6 +96,35 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
     return c > a ? c : a;
 }
 
+// Minimum over the wave of each of eight values per lane, all at once:
+// swaps between the two 32-lane halves and then between 16-lane rows leave
+// every lane with one of the values reduced over the four lanes of its
+// position (value j + 2 r in row r, j = 0 or 1); a row mirror pairs the two
+// halves of a row for j = 0 (lanes 0-7 of the row) and j = 1 (lanes 8-15),
+// and three DPP steps finish within each half.  Lane l returns the minimum
+// of value 2 (l / 16) + (l / 8) % 2.  Every lane of the wave must be active.
+__device__ __forceinline__ float wave_min8_f32(const float v[8], int lane) {
+    float w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 4]), false, false);
+        w[j] = fminf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+    }
+    float x[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[j]), __float_as_uint(w[j + 2]), false, false);
+        x[j] = fminf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+    }
+    const float m0 = fminf(x[0], dpp_f32<kDppRowMirror>(x[0]));
+    const float m1 = fminf(x[1], dpp_f32<kDppRowMirror>(x[1]));
+    float y = (lane & 8) ? m1 : m0;
+    y = fminf(y, dpp_f32<kDppQuad1032>(y));
+    y = fminf(y, dpp_f32<kDppQuad2301>(y));
+    y = fminf(y, dpp_f32<kDppRowHalfMirror>(y));
+    return y;
+}
+
 // Order-preserving map of a float to 32 bits (NaN ranks below -inf).
 __device__ __forceinline__ uint32_t ordered_f32(float f) {
     if (f != f) return 0u;
