@@ -666,7 +666,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                             const int j = tid + i * NT;
                             pe[i] = j < n_vis ? tile[j] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
                         }
-                        n_pre = min(PRE, (n_vis + NT - 1) / NT);         // uniform
+                        n_pre = min(PRE, (n_vis + NT - 1) / NT + 1) & ~1;   // uniform, even (pe beyond n_vis is far)
                     } else {
                         // this lane's four-entry groups as its loads brought
                         // them, in the staging's arithmetic; entries the
@@ -714,11 +714,13 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                             const float kvv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kkv), r));
                             const float clv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kclf), r));
 #pragma unroll
-                            for (int i = 0; i < PRE; ++i) {
-                                if (i < n_pre) {                         // uniform
-                                    const float hq = fmaf(pe[i].x, ch, pe[i].y * sh);
-                                    const float u = fmaf(kvv, hq, pe[i].w);
-                                    m = fminf(m, fmaf(clv, pe[i].z, u));
+                            for (int i = 0; i < PRE; i += 2) {
+                                if (i < n_pre) {                         // uniform; n_pre is even
+                                    const float hq0 = fmaf(pe[i].x, ch, pe[i].y * sh);
+                                    const float hq1 = fmaf(pe[i + 1].x, ch, pe[i + 1].y * sh);
+                                    const float u0 = fmaf(kvv, hq0, pe[i].w);
+                                    const float u1 = fmaf(kvv, hq1, pe[i + 1].w);
+                                    m = fminf(m, fminf(fmaf(clv, pe[i].z, u0), fmaf(clv, pe[i + 1].z, u1)));
                                 }
                             }
                         }
