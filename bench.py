@@ -36,8 +36,8 @@ FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared dist
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "planner.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "434e17a3e82d05150b3c6a2ca6adcac5e8d0fd7c202dd54e288b5141ac35e4b3"
-TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 8.05e8, "full_sweep": 3.98e8}
+TRAFFIC_SHA256 = "42cf05f5378d6c5f08dcf6f8d2c1617d53627006af12bb5fae044e037fadcd9d"
+TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 8.95e8, "full_sweep": 3.99e8}
 
 
 def _traffic(leg: str):
