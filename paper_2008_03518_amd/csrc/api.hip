@@ -62,6 +62,7 @@ struct fastmdp_ctx {
     float *dEvF = nullptr;        // proposal eval outputs: features, logits
     int *dEvI = nullptr;          // top-k, certified, proposal's action
     int *dStop = nullptr;         // finished-workgroup counter of a planner launch
+    int *dPass = nullptr;         // slots of an acceptance pass
     std::mutex mu;
     // counters of the last call
     long long st_pairs = 0, st_steps = 0, st_resumes = 0, st_launches = 0;
@@ -103,7 +104,7 @@ void free_all(fastmdp_ctx *c) {
     if (c->hSlots) hipHostFree(c->hSlots);
     if (c->hGather) hipHostFree(c->hGather);
     hipFree(c->dGather); hipFree(c->dList2); hipFree(c->dOff);
-    hipFree(c->dEvF); hipFree(c->dEvI); hipFree(c->dStop);
+    hipFree(c->dEvF); hipFree(c->dEvI); hipFree(c->dStop); hipFree(c->dPass);
     if (c->e0) hipEventDestroy(c->e0);
     if (c->e1) hipEventDestroy(c->e1);
     if (c->own) hipStreamDestroy(c->own);
@@ -170,8 +171,17 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.max_steps = c.max_steps;
 }
 
+// Adds the last planner launch's duration (its events have completed).
+int planner_time(fastmdp_ctx *c) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->e0, c->e1));
+    c->st_ms += ms;
+    c->st_launches += 1;
+    return 0;
+}
+
 int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int validate, int epoch,
-                  const EvalOut &ev, int stop_target = 0) {
+                  const EvalOut &ev, int stop_target = 0, bool sync = true) {
     const int nt = fmdp::kPlanThreads;
     HIP_TRY(hipEventRecord(c->e0, c->stream));
     const fmdp::LaunchStop stop{c->dStop, stop_target};
@@ -183,12 +193,9 @@ int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int val
         return FASTMDP_E_DEVICE;
     }
     HIP_TRY(hipEventRecord(c->e1, c->stream));
+    if (!sync) return 0;                     // the caller synchronises, then calls planner_time
     HIP_TRY(hipEventSynchronize(c->e1));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, c->e0, c->e1));
-    c->st_ms += ms;
-    c->st_launches += 1;
-    return 0;
+    return planner_time(c);
 }
 
 void reset_stats(fastmdp_ctx *c) {
@@ -228,19 +235,34 @@ int copy_plan_out(fastmdp_ctx *c, int slot, const Slot &s, fastmdp_plan *out) {
 
 // Copy the trajectories of accepted slots to the callers' plans: one gather
 // kernel into a device staging buffer, one copy into pinned host memory.
-int gather_plans_out(fastmdp_ctx *c, const std::vector<int> &slots, const std::vector<int> &reqs, const Slot *hs,
-                     fastmdp_plan *plans) {
-    const int m = (int)slots.size();
-    std::vector<long long> off(m);
+// Accepted trajectories on their way to the caller's plans: the device
+// packs them into one buffer and copies it to pinned host memory; the host
+// unpacks after a later synchronisation.
+struct PendingPlans {
+    std::vector<int> slots, reqs, n, status, t0;
+    std::vector<long long> off;
     long long total = 0;
+    bool empty() const { return reqs.empty(); }
+};
+
+int gather_enqueue(fastmdp_ctx *c, const std::vector<int> &slots, const std::vector<int> &reqs, const Slot *hs,
+                   const fastmdp_plan *plans, PendingPlans &pp) {
+    const int m = (int)slots.size();
+    pp = PendingPlans();
+    pp.slots = slots;
+    pp.reqs = reqs;
+    pp.off.resize(m);
     for (int i = 0; i < m; ++i) {
-        const int n = hs[slots[i]].n_points;
-        if (plans[reqs[i]].capacity < n) return FASTMDP_E_CAPACITY;
-        off[i] = total;
-        total += n;
+        const Slot &s = hs[slots[i]];
+        if (plans[reqs[i]].capacity < s.n_points) return FASTMDP_E_CAPACITY;
+        pp.off[i] = pp.total;
+        pp.total += s.n_points;
+        pp.n.push_back(s.n_points);
+        pp.status.push_back(s.status);
+        pp.t0.push_back(s.t0);
     }
-    const size_t bytes = (size_t)total * (3 * sizeof(double) + sizeof(double) + sizeof(int));
-    if (bytes > c->gather_cap) {
+    const size_t bytes = (size_t)pp.total * (3 * sizeof(double) + sizeof(double) + sizeof(int));
+    if (bytes > c->gather_cap) {            // no copy is in flight here: the last one was unpacked
         const size_t cap = std::max(bytes, 2 * c->gather_cap);
         hipFree(c->dGather);
         if (c->hGather) hipHostFree(c->hGather);
@@ -250,26 +272,29 @@ int gather_plans_out(fastmdp_ctx *c, const std::vector<int> &slots, const std::v
             return FASTMDP_E_NOMEM;
         c->gather_cap = cap;
     }
-    HIP_TRY(hipMemcpyAsync(c->dList2, slots.data(), m * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->dOff, off.data(), m * sizeof(long long), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(fmdp::launch_gather_traj(c->dSlots, c->dList2, m, c->dOff, total, c->tr, c->dGather, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->dList2, pp.slots.data(), m * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->dOff, pp.off.data(), m * sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(fmdp::launch_gather_traj(c->dSlots, c->dList2, m, c->dOff, pp.total, c->tr, c->dGather, c->stream));
     HIP_TRY(hipMemcpyAsync(c->hGather, c->dGather, bytes, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+// After a synchronisation that follows gather_enqueue.
+void gather_unpack(fastmdp_ctx *c, PendingPlans &pp, fastmdp_plan *plans) {
     const double *xyz = static_cast<const double *>(c->hGather);
-    const double *val = xyz + 3 * total;
-    const int *act = reinterpret_cast<const int *>(val + total);
-    for (int i = 0; i < m; ++i) {
-        const Slot &s = hs[slots[i]];
-        fastmdp_plan &p = plans[reqs[i]];
-        const int n = s.n_points;
-        std::memcpy(p.xyz, xyz + 3 * off[i], (size_t)n * 3 * sizeof(double));
-        std::memcpy(p.action, act + off[i], (size_t)n * sizeof(int));
-        std::memcpy(p.value, val + off[i], (size_t)n * sizeof(double));
-        p.status = s.status;
-        p.t0 = s.t0;
+    const double *val = xyz + 3 * pp.total;
+    const int *act = reinterpret_cast<const int *>(val + pp.total);
+    for (size_t i = 0; i < pp.reqs.size(); ++i) {
+        fastmdp_plan &p = plans[pp.reqs[i]];
+        const int n = pp.n[i];
+        std::memcpy(p.xyz, xyz + 3 * pp.off[i], (size_t)n * 3 * sizeof(double));
+        std::memcpy(p.action, act + pp.off[i], (size_t)n * sizeof(int));
+        std::memcpy(p.value, val + pp.off[i], (size_t)n * sizeof(double));
+        p.status = pp.status[i];
+        p.t0 = pp.t0[i];
         p.n_points = n;
     }
-    return 0;
+    pp = PendingPlans();
 }
 
 }  // namespace
@@ -316,7 +341,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->tr.col, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.nd, ssz);
     c->dl_cap = 1 << 22;
-    c->dl_start_cap = 1 << 16;
+    c->dl_start_cap = 1 << 20;             // one epoch per acceptance round
     rc = rc ? rc : dev_alloc(&c->dDlRow, (size_t)c->dl_cap);
     rc = rc ? rc : dev_alloc(&c->dDlCol, (size_t)c->dl_cap);
     rc = rc ? rc : dev_alloc(&c->dDlEp, (size_t)c->dl_cap);
@@ -331,6 +356,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->dEvF, (size_t)FASTMDP_N_FEAT + fmdp::kMaxActions);
     rc = rc ? rc : dev_alloc(&c->dEvI, (size_t)FASTMDP_MAX_TOPK + 2);
     rc = rc ? rc : dev_alloc(&c->dStop, (size_t)1);
+    rc = rc ? rc : dev_alloc(&c->dPass, (size_t)c->max_slots);
     if (!rc && hipHostMalloc(reinterpret_cast<void **>(&c->hSlots), (size_t)c->max_slots * sizeof(Slot)) != hipSuccess)
         rc = FASTMDP_E_NOMEM;
     if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
@@ -537,7 +563,8 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
     std::vector<int> slot_req(S, -1);        // request held by each slot
     std::vector<int> req_slot(n, -1);
     int next_req = 0, next_commit = 0;
-    std::vector<int> list;
+    std::vector<int> list, pass;
+    PendingPlans pending;                    // accepted trajectories still being copied
     // withdrawal log of this call: epoch e's withdrawals start at dl_start[e]
     int epoch = 0, dl_len = 0;
     std::vector<int> dl_start(2, 0);
@@ -584,7 +611,13 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.001)));
             continue;
         }
-        if (!list.empty()) {
+        // One synchronisation per round: the planner launch, the acceptance
+        // pass over every admitted, not yet accepted request (its kernels
+        // skip the ones still planning), the copy of the slots back, and the
+        // trajectories accepted in the previous round on their way to the
+        // caller's plans, all in stream order.
+        const bool planned = !list.empty();
+        if (planned) {
             HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
             EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -592,32 +625,32 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             // the others resume after the acceptance pass, with new requests
             // in the freed compute units
             const int stop_target = std::max(1, (int)list.size() / 4);
-            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, epoch, none, stop_target);
+            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, epoch, none, stop_target, false);
             if (rc) return finish(rc);
-            HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
-            HIP_TRY(hipStreamSynchronize(ctx->stream));
         }
-        // pass over every finished, not yet accepted request
-        list.clear();
-        for (int r = next_commit; r < next_req; ++r)
-            if (hs[req_slot[r]].status != fmdp::kRunning) list.push_back(req_slot[r]);
-        if (list.empty()) continue;
+        pass.clear();
+        for (int r = next_commit; r < next_req; ++r) pass.push_back(req_slot[r]);
         epoch += 1;
         if (epoch + 1 >= ctx->dl_start_cap) return finish(FASTMDP_E_CAPACITY);
         dl_start.resize(epoch + 1);
         dl_start[epoch] = dl_len;
         HIP_TRY(hipMemcpyAsync(ctx->dDlStart + epoch, &dl_start[epoch], sizeof(int), hipMemcpyHostToDevice,
                                ctx->stream));
-        HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dList, (int)list.size(), ctx->tr, dl, epoch,
+        HIP_TRY(hipMemcpyAsync(ctx->dPass, pass.data(), pass.size() * sizeof(int), hipMemcpyHostToDevice,
+                               ctx->stream));
+        HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dPass, (int)pass.size(), ctx->tr, dl, epoch,
                                        ctx->stream));
         HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipMemcpyAsync(&dl_len, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if (planned) {
+            int rc = planner_time(ctx);
+            if (rc) return finish(rc);
+        }
+        if (!pending.empty()) gather_unpack(ctx, pending, plans);
         if (dl_len > ctx->dl_cap) return finish(FASTMDP_E_CAPACITY);
-        for (int s : list) {
+        for (int s : pass) {
             if (hs[s].err) return finish(FASTMDP_E_CAPACITY);
-            if (hs[s].status == fmdp::kRunning) ctx->st_resumes += 1;
         }
         // accept in request order: a finished request whose predecessors are
         // all accepted is final; one that withdrew entries in this pass ends
@@ -635,16 +668,21 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             ctx->st_steps += hs[s].steps;
             ctx->st_hit += hs[s].cert_hit;
             ctx->st_miss += hs[s].cert_miss;
+            ctx->st_resumes += hs[s].resumes;
             acc_slots.push_back(s);
             acc_reqs.push_back(r);
             ++next_commit;
             if (hs[s].killed) break;
         }
         if (!acc_slots.empty()) {
-            int rc = gather_plans_out(ctx, acc_slots, acc_reqs, hs, plans);
+            int rc = gather_enqueue(ctx, acc_slots, acc_reqs, hs, plans, pending);
             if (rc) return finish(rc);
-            for (int s : acc_slots) slot_req[s] = -1;
+            for (int s : acc_slots) slot_req[s] = -1;   // reusable: the gather precedes any new planning
         }
+    }
+    if (!pending.empty()) {
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        gather_unpack(ctx, pending, plans);
     }
     ctx->seq = seq0 + n;
     return finish(0);

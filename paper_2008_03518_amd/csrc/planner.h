@@ -76,6 +76,7 @@ struct Slot {
     int cert_hit;     // proposal steps certified, accumulated
     int cert_miss;    // proposal steps that fell back to the full sweep, accumulated
     int first;        // FCFS check: first affected point found so far (INT_MAX if none)
+    int resumes;      // FCFS: times the request went back to planning, accumulated
 };
 
 // Per-slot trajectory buffers, `stride` points per slot.  seen[k] is the

@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, 
                                                                    Traj tr) {
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
+    if (S.status == kRunning) return;                        // still planning: not in this pass
     if (threadIdx.x == 0) S.first = 0x7fffffff;             // opened here for the checks that follow
     if (S.status != FASTMDP_OK || !S.valid) return;
     const int n = S.n_points, t0 = S.t0, own = S.seq;
@@ -168,6 +169,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
     const int tid = threadIdx.x;
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
+    if (S.status == kRunning) return;                        // still planning: not in this pass
     const int n = S.n_points, t0 = S.t0, q = S.seq;
     const size_t base = (size_t)slot * tr.stride;
     if (tid == 0) { s_first = 0x7fffffff; s_minep = 0x7fffffff; }
@@ -208,6 +210,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
+    if (S.status == kRunning) return;                        // still planning: not in this pass
     const int n = S.n_points, t0 = S.t0, q = S.seq;
     const int k0 = blockIdx.y * kCheckPoints;
     if (k0 >= n) return;
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_finish_kernel(DevTabl
     const int tid = threadIdx.x;
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
+    if (S.status == kRunning) return;                        // still planning: not in this pass
     const int n = S.n_points, t0 = S.t0, first = S.first;
     const size_t base = (size_t)slot * tr.stride;
     for (int k = tid; k < min(n, first); k += kPassThreads) {
@@ -277,6 +281,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_withdraw_kernel(DevTable tb
     const int tid = threadIdx.x;
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
+    if (S.status == kRunning) return;                        // still planning: not in this pass
     const int n = S.n_points, t0 = S.t0;
     const size_t base = (size_t)slot * tr.stride;
     int from = n;
@@ -311,6 +316,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_withdraw_kernel(DevTable tb
             S.n_points = S.resume_at;   // keep points 0..resume_at-1; re-score from the last kept point
             S.status = kRunning;
             S.valid = 0;
+            S.resumes += 1;
         }
     }
 }

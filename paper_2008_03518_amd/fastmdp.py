@@ -290,6 +290,22 @@ class Plan:
         return self.value[: self.n_points]
 
 
+# fastmdp_request as a NumPy record (same layout as _Request), so that a
+# batch of requests is marshalled without a Python loop
+_REQUEST_DTYPE = np.dtype({"names": ["id", "origin", "goal", "t0"],
+                           "formats": ["<u8", ("<f8", 3), ("<f8", 3), "<i4"],
+                           "offsets": [0, 8, 32, 56], "itemsize": 64})
+
+
+def _request_array(requests, m: int) -> np.ndarray:
+    a = np.zeros(max(m, 1), dtype=_REQUEST_DTYPE)
+    a["id"][:m] = np.asarray(requests.ident[:m], dtype=np.uint64)
+    a["origin"][:m] = np.asarray(requests.origin[:m], dtype=np.float64)
+    a["goal"][:m] = np.asarray(requests.goal[:m], dtype=np.float64)
+    a["t0"][:m] = np.asarray(requests.t0[:m], dtype=np.int32)
+    return a
+
+
 def _request(origin, goal, t0: int, ident: int = 0) -> _Request:
     r = _Request()
     r.id = int(ident)
@@ -389,9 +405,8 @@ class Context:
         acceptance time of each request in seconds since the call started.
         """
         m = requests.n if limit is None else min(limit, requests.n)
-        arr = (_Request * max(m, 1))()
-        for k in range(m):
-            arr[k] = _request(requests.origin[k], requests.goal[k], int(requests.t0[k]), int(requests.ident[k]))
+        reqa = _request_array(requests, m)
+        arr = reqa.ctypes.data_as(C.POINTER(_Request))
         if out is not None and len(out) >= m and all(p.c.capacity >= self.capacity for p in out[:m]):
             plans = list(out[:m])
         else:

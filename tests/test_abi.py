@@ -91,3 +91,18 @@ def test_create_rejects_invalid_configs():
     assert create(max_steps=16383 + 1) == fm.E_INVAL
     assert create(max_rows=1) == fm.E_INVAL
     assert fm._lib.fastmdp_create(None, ctypes.byref(out)) == fm.E_INVAL
+
+
+def test_request_batch_layout_matches_struct():
+    """The vectorised request marshalling writes the fastmdp_request bytes."""
+    _lib_path()
+    from paper_2008_03518_amd import fastmdp as fm
+    from paper_2008_03518_amd import scenario as S
+    assert ctypes.sizeof(fm._Request) == fm._REQUEST_DTYPE.itemsize
+    sc = S.small(seed=0, n_requests=5)
+    req = sc.requests
+    a = fm._request_array(req, req.n)
+    p = a.ctypes.data_as(ctypes.POINTER(fm._Request))
+    for k in range(req.n):
+        r = fm._request(req.origin[k], req.goal[k], int(req.t0[k]), int(req.ident[k]))
+        assert bytes(p[k]) == bytes(r), k
