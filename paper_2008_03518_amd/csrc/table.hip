@@ -217,25 +217,34 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
     const size_t base = (size_t)slot * tr.stride;
     const double r2 = c.reach * c.reach;
     constexpr int per_wave = kCheckPoints / (kPassThreads / 64);
-    for (int i = 0; i < per_wave; ++i) {
-        const int k = k0 + wave * per_wave + i;             // wave-uniform
-        if (k >= n) break;
+    static_assert(per_wave <= 64, "one lane per point of the wave");
+    // the bookkeeping of the wave's points, one lane each, read at once;
+    // then only the points whose row gained entries are scanned, in order
+    const int kl = k0 + wave * per_wave + lane;
+    int lo = 0, hi = 0, top = -1;
+    if (lane < per_wave && kl < n && t0 + kl < tb.rows) {
+        hi = min(tb.rowN[t0 + kl], tb.cap);
+        lo = tr.seen[base + kl];
+        top = kl > 0 ? tr.top[base + kl] : -1;
+    }
+    uint64_t todo = __ballot(lane < per_wave && lo < hi);
+    while (todo) {                                        // wave-uniform
+        const int i = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int k = k0 + wave * per_wave + i;
         const int row = t0 + k;
-        if (row >= tb.rows) break;
-        const int hi = min(tb.rowN[row], tb.cap);
-        const int lo = tr.seen[base + k];
-        if (lo >= hi) continue;
+        const int lo_k = __builtin_amdgcn_readlane(lo, i), hi_k = __builtin_amdgcn_readlane(hi, i);
+        const int top_k = __builtin_amdgcn_readlane(top, i);
         const double *x = tr.xyz + (base + k) * 3;         // chosen successor (the origin for k = 0)
         double y[3] = {x[0], x[1], x[2]};                  // largest action's successor, if different
-        const int top = k > 0 ? tr.top[base + k] : -1;
-        if (top >= 0) {
+        if (top_k >= 0) {
             const double *sp = tr.xyz + (base + k - 1) * 3;
             const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
             const double r = sqrt(bx * bx + by * by);
             const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
-            const int h = top / (c.n_climb * c.n_speed);
-            const int cl = (top / c.n_speed) % c.n_climb;
-            const int v = top % c.n_speed;
+            const int h = top_k / (c.n_climb * c.n_speed);
+            const int cl = (top_k / c.n_speed) % c.n_climb;
+            const int v = top_k % c.n_speed;
             const double th = 2.0 * M_PI * (double)h / (double)c.n_head;
             const double c0 = cos(th), s0 = sin(th);
             const double step = c.speed[v] * c.dt;
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
         }
         const size_t rb = (size_t)row * tb.cap;
         int hit = 0;
-        for (int j = lo + lane; j < hi && !hit; j += 64) {
+        for (int j = lo_k + lane; j < hi_k && !hit; j += 64) {
             if (!entry_visible(tb, rb + j, q)) continue;
             const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
             hit = entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2;
