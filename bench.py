@@ -144,6 +144,60 @@ def _calibrate_copy():
                                            "written_bytes": n * row}}), flush=True)
 
 
+def serving_stats(arrival_s, done_s) -> dict:
+    """Latency and queue statistics of one open-loop serving pass.
+
+    Latency of a request = its acceptance time minus its scheduled arrival.
+    Queue depth = requests in the system (arrived, not yet accepted) seen by
+    each arrival, itself included: arrival i finds i + 1 arrivals so far, less
+    those already accepted (acceptances never precede their arrival).
+    """
+    arr = np.asarray(arrival_s, dtype=np.float64)
+    done = np.asarray(done_s, dtype=np.float64)
+    lat = (done - arr) * 1e3
+    gone = np.searchsorted(np.sort(done), arr, side="right")
+    depth = np.arange(1, arr.size + 1) - gone
+    return {"p50_latency_ms": float(np.percentile(lat, 50)),
+            "p99_latency_ms": float(np.percentile(lat, 99)),
+            "mean_queue_depth": float(depth.mean()),
+            "max_queue_depth": int(depth.max())}
+
+
+def _serve(ctx, sc, S, rate, m):
+    """One Poisson-arrival serving pass of m requests at ``rate`` req/s from
+    the rewound table, with the proposal the context has selected."""
+    sreq = S.Requests(sc.requests.ident[:m], sc.requests.origin[:m], sc.requests.goal[:m], sc.requests.t0[:m])
+    arr = S.serving_arrivals(rate, m, seed=3)
+    ctx.rewind()
+    t = time.perf_counter()
+    _, scom, sdone = ctx.plan_fcfs(sreq, arrival_s=arr)
+    el = time.perf_counter() - t
+    st = ctx.stats()
+    out = {"rate_req_s": rate, "requests": m, "achieved_req_s": m / el}
+    out.update(serving_stats(arr, sdone))
+    out.update({"committed": int(scom.sum()), "resumes_per_request": st["resumes"] / m})
+    return out
+
+
+def _sequential(ctx, reqs, n, full):
+    """The first n requests planned and committed one at a time (one
+    workgroup each) with the full sweep, from the rewound table; their plans
+    must equal the concurrent pass's."""
+    from paper_2008_03518_amd import fastmdp as fm
+    ctx.set_proposal(fm.PROPOSE_NONE, 1, None, 1)
+    ctx.rewind()
+    plans, committed = [], []
+    t = time.perf_counter()
+    for q in range(n):
+        p = ctx.plan_request(reqs.origin[q], reqs.goal[q], int(reqs.t0[q]), int(reqs.ident[q]))
+        committed.append(bool(ctx.commit_plan(p)) if p.status == fm.OK else False)
+        plans.append(p)
+    el = time.perf_counter() - t
+    same = _same_plans(plans, full["plans"][:n]) and committed == [bool(c) for c in full["committed"][:n]]
+    return {"requests": n, "value": n / el, "ms_per_request": el / n * 1e3,
+            "identical_to_concurrent_pass": bool(same)}
+
+
 def _same_plans(a, b) -> bool:
     for p, q in zip(a, b):
         n = p.n_points
@@ -175,6 +229,13 @@ def main():
     ap.add_argument("--ablations", type=int, default=1, help="also time goal-ranked and untrained proposals")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals [req/s]; 0 disables")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rates", default="",
+                    help="also serve at each of these comma-separated rates [req/s], "
+                         "min(--serve-requests, rate * --serve-seconds) arrivals each")
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--sequential", type=int, default=0,
+                    help="also plan the first N requests one at a time (plan, then commit) with the full "
+                         "sweep and compare with the concurrent pass; 0 disables")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work; 0 disables")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -285,24 +346,30 @@ def main():
                                                "pair_evals": prop["pairs"] / len(prop["times"])}
         untrained.close()
 
-    if args.serve_rate > 0:
-        m = args.serve_requests
-        sreq = S.Requests(sc.requests.ident[:m], sc.requests.origin[:m], sc.requests.goal[:m], sc.requests.t0[:m])
-        arr = S.serving_arrivals(args.serve_rate, m, seed=3)
+    if args.sequential > 0:
+        out["sequential_full_sweep"] = _sequential(ctx, reqs, min(args.sequential, reqs.n), full)
+        q = out["sequential_full_sweep"]
+        log(f"sequential full sweep, {q['requests']} requests: {q['value']:.1f} req/s, "
+            f"identical to the concurrent pass: {q['identical_to_concurrent_pass']}")
+
+    if args.serve_rate > 0 or args.serve_rates:
         ctx.set_proposal(fm.PROPOSE_MLP, args.top_k, net, args.refresh)
-        ctx.rewind()
-        t = time.perf_counter()
-        _, scom, sdone = ctx.plan_fcfs(sreq, arrival_s=arr)
-        el = time.perf_counter() - t
-        lat = (sdone - arr) * 1e3
-        out["serving"] = {"rate_req_s": args.serve_rate, "requests": m, "achieved_req_s": m / el,
-                          "p50_latency_ms": float(np.percentile(lat, 50)),
-                          "p99_latency_ms": float(np.percentile(lat, 99)),
-                          "committed": int(scom.sum())}
+    if args.serve_rate > 0:
+        out["serving"] = _serve(ctx, sc, S, args.serve_rate, args.serve_requests)
         out["p50_latency_ms"] = out["serving"]["p50_latency_ms"]
         out["p99_latency_ms"] = out["serving"]["p99_latency_ms"]
         log(f"serving at {args.serve_rate} req/s: p50 {out['p50_latency_ms']:.1f} ms, "
             f"p99 {out['p99_latency_ms']:.1f} ms")
+    if args.serve_rates:
+        out["serving_sweep"] = []
+        for rate in (float(x) for x in args.serve_rates.split(",")):
+            m = max(1, min(args.serve_requests, int(rate * args.serve_seconds)))
+            r = _serve(ctx, sc, S, rate, m)
+            out["serving_sweep"].append(r)
+            log(f"serving at {rate:g} req/s ({m} requests): achieved {r['achieved_req_s']:.1f} req/s, "
+                f"p50 {r['p50_latency_ms']:.1f} ms, p99 {r['p99_latency_ms']:.1f} ms, "
+                f"queue mean {r['mean_queue_depth']:.2f} max {r['max_queue_depth']}, "
+                f"resumes/request {r['resumes_per_request']:.3f}")
     ctx.close()
     net.close()
 
