@@ -141,6 +141,44 @@ def test_large_actions_full_size_sampled(fm):
     _log(f"[3000 plans x 360 actions] {st}")
 
 
+def test_fcfs_full_size_bench_launch_config(fm):
+    """The 3000-plan, 360-action workload through the concurrent engine in the
+    benchmark's launch configuration (1024 slots, at most one request per
+    compute unit, 512 steps per launch, early end), on more requests than
+    compute units: every result equals sequential plan-then-commit bitwise,
+    and the first requests equal the oracle's own sequential planning."""
+    sc = S.large_actions(seed=2, n_plans=3000, n_requests=1000)
+    m = 300
+    reqs = S.Requests(sc.requests.ident[:m], sc.requests.origin[:m], sc.requests.goal[:m], sc.requests.t0[:m])
+    with fm.context_for(sc, max_slots=1024, steps_per_launch=512) as ctx:
+        ctx.snapshot()
+        plans, committed, _ = ctx.plan_fcfs(reqs)
+        st = ctx.stats()
+        _log(f"[fcfs full size] {st}, committed {int(committed.sum())}/{m}")
+        ctx.rewind()
+        seq = []
+        for q in range(m):
+            p = ctx.plan_request(reqs.origin[q], reqs.goal[q], int(reqs.t0[q]))
+            seq.append((p, ctx.commit_plan(p) if p.status == 0 else False))
+    assert st["launches"] > 1
+    for q, ((p, c), b, cb) in enumerate(zip(seq, plans, committed)):
+        assert p.status == b.status and p.n_points == b.n_points, q
+        assert np.array_equal(p.points(), b.points()) and np.array_equal(p.actions(), b.actions()), q
+        assert np.array_equal(p.values(), b.values()), q
+        assert c == cb, q
+    assert _separation_violations(sc, plans, committed) == 0
+    orc = Oracle(sc.cfg, sc.plans)
+    for q in range(2):
+        goal = reqs.goal[q]
+        op = orc.plan(reqs.origin[q], goal, int(reqs.t0[q]))
+        same, diverged = compare_trajectory(plans[q], op, orc, goal)
+        _log(f"[fcfs full size] request {q}: oracle status {op.status}, {op.n_points} points, "
+             f"identical {same}, diverged {diverged}")
+        if diverged:
+            break                 # the tables differ from here on
+        assert (orc.commit(op) if op.status == 0 else False) == bool(committed[q])
+
+
 def test_multi_tile_ragged_rows(fm):
     """Rows far larger than one LDS tile, with a ragged tail."""
     cfg = S.cfg_large_actions()
@@ -251,12 +289,16 @@ def test_determinism(fm):
 
 
 def _separation_violations(sc, plans, committed):
+    """Committed plans closer than R_sep to an earlier plan at a common row:
+    each plan's points as planned (FP64) against the earlier plans as the
+    table holds them (FP32), the comparison commit validation makes."""
     off = sc.plans.offsets()
     tabs = [(int(sc.plans.t0[j]), sc.plans.xyz[off[j]:off[j + 1]].astype(np.float64)) for j in range(sc.plans.n)]
     bad = 0
-    mine = [(p.t0, p.points().astype(np.float32).astype(np.float64)) for p, c in zip(plans, committed) if c]
+    mine = [(p.t0, p.points().copy()) for p, c in zip(plans, committed) if c]
+    stored = [(t, x.astype(np.float32).astype(np.float64)) for t, x in mine]
     for i, (ti, xi) in enumerate(mine):
-        for tj, xj in tabs + mine[:i]:
+        for tj, xj in tabs + stored[:i]:
             lo, hi = max(ti, tj), min(ti + len(xi), tj + len(xj))
             if lo < hi and np.min(np.linalg.norm(xi[lo - ti:hi - ti] - xj[lo - tj:hi - tj], axis=1)) < sc.cfg.R_sep:
                 bad += 1
