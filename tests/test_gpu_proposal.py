@@ -306,6 +306,29 @@ def test_proposal_plans_identical_to_full_sweep(fm):
     net.close()
 
 
+def test_proposal_identical_full_size_bench_launch_config(fm):
+    """The benchmark's launch configuration (1024 slots, 512 steps per launch,
+    top 8 re-ranked every 64 steps) on 300 requests at 3000 plans and 360
+    actions: the proposal path commits the full sweep's plans bit for bit."""
+    sc = S.large_actions(seed=2, n_plans=3000, n_requests=300)
+    A = sc.cfg.n_actions
+    net = fm.Mlp(A)
+    net.set_params(_params(A, 70))
+    with fm.context_for(sc, max_slots=1024, steps_per_launch=512) as ctx:
+        ctx.snapshot()
+        ref, com, st, _ = _run(ctx, sc.requests, fm.PROPOSE_NONE)
+        assert st["launches"] > 1
+        for name, mode, nt in (("goal", fm.PROPOSE_GOAL, None), ("untrained", fm.PROPOSE_MLP, net)):
+            plans, c2, st2, ps = _run(ctx, sc.requests, mode, nt, 8, 64)
+            _same_plans(plans, ref)
+            assert np.array_equal(c2, com)
+            tot = ps["certified"] + ps["fallbacks"]
+            _log(f"[identical full size] {name}: {ps['certified']}/{tot} steps certified, "
+                 f"{st2['launches']} launches, {st2['resumes']} resumes")
+            assert tot > 0
+    net.close()
+
+
 @pytest.mark.parametrize("preset", ["small", "paper_scale"])
 def test_proposal_plans_identical_other_shapes(fm, preset):
     """81 actions (9 x 3 x 3), with terrain for the paper-scale box: terrain
