@@ -203,6 +203,62 @@ def test_multi_tile_ragged_rows(fm):
         assert st["pairs"] == cfg.n_actions * n
 
 
+@pytest.mark.parametrize("n_head,climb,speed", [(34, (-5.0, -2.5, 0.0, 2.5, 5.0), (20.0, 30.0, 40.0)),
+                                                 (128, (-5.0, 0.0, 5.0), (30.0,))])
+def test_largest_action_sets(fm, n_head, climb, speed):
+    """The largest action sets the kernels take: 510 actions (34 headings x 5
+    climbs x 3 speeds) and 128 headings (x 3 climbs, one speed: 384
+    actions).  Per-action values
+    near plans and trajectories against the oracle; the proposal path's
+    plans against the full sweep's."""
+    sc = S.small(seed=21, n_plans=200, n_requests=6)
+    sc.cfg.n_head, sc.cfg.climb, sc.cfg.speed = n_head, climb, speed
+    sc.cfg.plan_capacity = 512                               # room for tentative entries
+    A = sc.cfg.n_actions
+    assert A in (510, 384)
+    orc = Oracle(sc.cfg, sc.plans)
+    with fm.context_for(sc) as ctx:
+        for s, g, t in _states_near_plans(sc, 6, seed=4):
+            compare_eval(ctx.eval_step(s, g, t), orc.eval_step(s, g, t))
+    st = _fcfs_sync(fm, sc, 3, teacher_every=0)
+    _log(f"[{A} actions] {st}")
+    with fm.context_for(sc, max_slots=8) as ctx:
+        ctx.snapshot()
+        ctx.set_proposal(fm.PROPOSE_NONE, 1)
+        ref, com, _ = ctx.plan_fcfs(sc.requests)
+        ctx.rewind()
+        ctx.set_proposal(fm.PROPOSE_GOAL, 8, None, 4)
+        got, com2, _ = ctx.plan_fcfs(sc.requests)
+        ps = ctx.proposal_stats()
+    _log(f"[{A} actions] proposal: {ps}")
+    assert np.array_equal(com, com2)
+    for p, q in zip(ref, got):
+        assert p.status == q.status and np.array_equal(p.points(), q.points())
+        assert np.array_equal(p.actions(), q.actions()) and np.array_equal(p.values(), q.values())
+
+
+def test_degenerate_requests(fm):
+    """Capture at the origin (one point), a goal straight above the origin
+    (no horizontal bearing: heading offsets from 0), and an empty batch."""
+    sc = S.small(seed=22, n_plans=100, n_requests=1)
+    orc = Oracle(sc.cfg, sc.plans)
+    o = np.array([300.0, 9700.0, 500.0])
+    cases = [(o, o + [5.0, -5.0, 3.0]), (o, o + [0.0, 0.0, 300.0])]
+    with fm.context_for(sc) as ctx:
+        n0 = ctx.n_plans
+        for k, (a, g) in enumerate(cases):
+            gp = ctx.plan_request(a, g, 0)
+            op = orc.plan(a, g, 0)
+            same, diverged = compare_trajectory(gp, op, orc, g)
+            _log(f"[degenerate {k}] status {op.status}, {op.n_points} points, identical {same}")
+            assert not diverged
+            if k == 0:
+                assert op.status == fm.OK and op.n_points == 1 and gp.n_points == 1
+        empty = S.Requests(np.zeros(0, np.uint64), np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.int32))
+        plans, committed, done = ctx.plan_fcfs(empty)
+        assert len(plans) == 0 and committed.size == 0 and done.size == 0 and ctx.n_plans == n0
+
+
 def test_empty_table_straight_track(fm):
     cfg = S.cfg_large_actions()
     o, g = np.array([1000.0, 5000.0, 300.0]), np.array([9030.0, 5000.0, 300.0])
