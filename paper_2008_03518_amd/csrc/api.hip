@@ -57,6 +57,15 @@ struct fastmdp_ctx {
     void *dGather = nullptr, *hGather = nullptr;
     size_t gather_cap = 0;                // bytes
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t eGather = nullptr;         // after the last trajectory gather's copy to the host
+    // pinned staging of the engine's small per-round transfers (the copies
+    // read or write it when the stream reaches them, so each region is
+    // rewritten only after the round's synchronisation): gather offsets, the
+    // launch list, the pass list, the gather list, and the withdrawal log's
+    // epoch start and length
+    void *hRound = nullptr;
+    long long *hOff = nullptr;
+    int *hList = nullptr, *hPass = nullptr, *hList2 = nullptr, *hDl = nullptr;
     // learned action proposal
     fmdp::PropArgs prop{};
     float *dEvF = nullptr;        // proposal eval outputs: features, logits
@@ -107,6 +116,8 @@ void free_all(fastmdp_ctx *c) {
     hipFree(c->dEvF); hipFree(c->dEvI); hipFree(c->dStop); hipFree(c->dPass);
     if (c->e0) hipEventDestroy(c->e0);
     if (c->e1) hipEventDestroy(c->e1);
+    if (c->eGather) hipEventDestroy(c->eGather);
+    if (c->hRound) hipHostFree(c->hRound);
     if (c->own) hipStreamDestroy(c->own);
 }
 
@@ -272,10 +283,14 @@ int gather_enqueue(fastmdp_ctx *c, const std::vector<int> &slots, const std::vec
             return FASTMDP_E_NOMEM;
         c->gather_cap = cap;
     }
-    HIP_TRY(hipMemcpyAsync(c->dList2, pp.slots.data(), m * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->dOff, pp.off.data(), m * sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    if (m > c->max_slots) return FASTMDP_E_CAPACITY;
+    std::memcpy(c->hList2, pp.slots.data(), m * sizeof(int));
+    std::memcpy(c->hOff, pp.off.data(), m * sizeof(long long));
+    HIP_TRY(hipMemcpyAsync(c->dList2, c->hList2, m * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->dOff, c->hOff, m * sizeof(long long), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(fmdp::launch_gather_traj(c->dSlots, c->dList2, m, c->dOff, pp.total, c->tr, c->dGather, c->stream));
     HIP_TRY(hipMemcpyAsync(c->hGather, c->dGather, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipEventRecord(c->eGather, c->stream));
     return 0;
 }
 
@@ -362,6 +377,19 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
     if (!rc && hipEventCreate(&c->e0) != hipSuccess) rc = FASTMDP_E_DEVICE;
     if (!rc && hipEventCreate(&c->e1) != hipSuccess) rc = FASTMDP_E_DEVICE;
+    if (!rc && hipEventCreateWithFlags(&c->eGather, hipEventDisableTiming) != hipSuccess) rc = FASTMDP_E_DEVICE;
+    if (!rc) {
+        const size_t ms = (size_t)c->max_slots;
+        if (hipHostMalloc(&c->hRound, ms * sizeof(long long) + (4 * ms + 2) * sizeof(int)) != hipSuccess) {
+            rc = FASTMDP_E_NOMEM;
+        } else {
+            c->hOff = static_cast<long long *>(c->hRound);
+            c->hList = reinterpret_cast<int *>(c->hOff + ms);
+            c->hPass = c->hList + ms;
+            c->hList2 = c->hPass + ms;
+            c->hDl = c->hList2 + ms;
+        }
+    }
     if (rc) {
         free_all(c);
         delete c;
@@ -618,7 +646,8 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
         // caller's plans, all in stream order.
         const bool planned = !list.empty();
         if (planned) {
-            HIP_TRY(hipMemcpyAsync(ctx->dList, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice,
+            std::memcpy(ctx->hList, list.data(), list.size() * sizeof(int));
+            HIP_TRY(hipMemcpyAsync(ctx->dList, ctx->hList, list.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
             EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
             // the launch ends once a quarter of its requests have finished:
@@ -634,20 +663,27 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
         if (epoch + 1 >= ctx->dl_start_cap) return finish(FASTMDP_E_CAPACITY);
         dl_start.resize(epoch + 1);
         dl_start[epoch] = dl_len;
-        HIP_TRY(hipMemcpyAsync(ctx->dDlStart + epoch, &dl_start[epoch], sizeof(int), hipMemcpyHostToDevice,
-                               ctx->stream));
-        HIP_TRY(hipMemcpyAsync(ctx->dPass, pass.data(), pass.size() * sizeof(int), hipMemcpyHostToDevice,
+        ctx->hDl[0] = dl_len;
+        std::memcpy(ctx->hPass, pass.data(), pass.size() * sizeof(int));
+        HIP_TRY(hipMemcpyAsync(ctx->dDlStart + epoch, ctx->hDl, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->dPass, ctx->hPass, pass.size() * sizeof(int), hipMemcpyHostToDevice,
                                ctx->stream));
         HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dPass, (int)pass.size(), ctx->tr, dl, epoch,
                                        ctx->stream));
         HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(hipMemcpyAsync(&dl_len, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->hDl + 1, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        // the trajectories accepted last round were gathered ahead of this
+        // round's launch: hand them to the caller while the planner runs
+        if (!pending.empty()) {
+            HIP_TRY(hipEventSynchronize(ctx->eGather));
+            gather_unpack(ctx, pending, plans);
+        }
         HIP_TRY(hipStreamSynchronize(ctx->stream));
+        dl_len = ctx->hDl[1];
         if (planned) {
             int rc = planner_time(ctx);
             if (rc) return finish(rc);
         }
-        if (!pending.empty()) gather_unpack(ctx, pending, plans);
         if (dl_len > ctx->dl_cap) return finish(FASTMDP_E_CAPACITY);
         for (int s : pass) {
             if (hs[s].err) return finish(FASTMDP_E_CAPACITY);
