@@ -37,7 +37,7 @@ FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared dist
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "planner.h", "proposal.h", "wave.h")
 TRAFFIC_SHA256 = "f1286343271a72eabc00b4f553382b56f579ff566382c44bbeff2dac9ae85dfd"
-TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 9.00e8, "full_sweep": 4.16e8}
+TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 8.95e8, "full_sweep": 4.00e8}
 
 
 def _traffic(leg: str):
