@@ -259,6 +259,38 @@ def test_degenerate_requests(fm):
         assert len(plans) == 0 and committed.size == 0 and done.size == 0 and ctx.n_plans == n0
 
 
+def test_planning_rows_beyond_one_tile(fm):
+    """Planning (not only single steps) on rows of more plans than one LDS
+    tile holds: 5000 known plans, so the first rows hold ~5000 entries.  The
+    concurrent full sweep equals sequential plan-then-commit bitwise, the
+    proposal path (which sweeps such rows in full) equals it too, and the
+    first request equals the oracle's."""
+    sc = S.large_actions(seed=31, n_plans=5000, n_requests=24)
+    assert int(np.sum(sc.plans.t0 == 0)) > 4096
+    seq = []
+    with fm.context_for(sc) as ctx:
+        for q in range(sc.requests.n):
+            p = ctx.plan_request(sc.requests.origin[q], sc.requests.goal[q], int(sc.requests.t0[q]))
+            seq.append((p, ctx.commit_plan(p) if p.status == 0 else False))
+    with fm.context_for(sc, max_slots=32, steps_per_launch=512) as ctx:
+        ctx.snapshot()
+        for mode in (fm.PROPOSE_NONE, fm.PROPOSE_GOAL):
+            ctx.rewind()
+            ctx.set_proposal(mode, 8, None, 64)
+            plans, committed, _ = ctx.plan_fcfs(sc.requests)
+            _log(f"[rows beyond one tile] mode {mode}: {ctx.stats()}, committed {int(committed.sum())}")
+            for q, ((p, c), b, cb) in enumerate(zip(seq, plans, committed)):
+                assert p.status == b.status and p.n_points == b.n_points, q
+                assert np.array_equal(p.points(), b.points()) and np.array_equal(p.actions(), b.actions()), q
+                assert np.array_equal(p.values(), b.values()), q
+                assert c == cb, q
+    orc = Oracle(sc.cfg, sc.plans)
+    goal = sc.requests.goal[0]
+    op = orc.plan(sc.requests.origin[0], goal, int(sc.requests.t0[0]))
+    same, diverged = compare_trajectory(seq[0][0], op, orc, goal)
+    _log(f"[rows beyond one tile] request 0: {op.n_points} points, identical {same}, diverged {diverged}")
+
+
 def test_empty_table_straight_track(fm):
     cfg = S.cfg_large_actions()
     o, g = np.array([1000.0, 5000.0, 300.0]), np.array([9030.0, 5000.0, 300.0])
