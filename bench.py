@@ -233,6 +233,9 @@ def main():
                     help="also serve at each of these comma-separated rates [req/s], "
                          "min(--serve-requests, rate * --serve-seconds) arrivals each")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--growth", type=int, default=0,
+                    help="also serve this many Poisson arrivals at --serve-rate from the known-plan table "
+                         "as it grows by every accepted plan (a table sized for all of them); 0 disables")
     ap.add_argument("--sequential", type=int, default=0,
                     help="also plan the first N requests one at a time (plan, then commit) with the full "
                          "sweep and compare with the concurrent pass; 0 disables")
@@ -370,6 +373,22 @@ def main():
                 f"p50 {r['p50_latency_ms']:.1f} ms, p99 {r['p99_latency_ms']:.1f} ms, "
                 f"queue mean {r['mean_queue_depth']:.2f} max {r['max_queue_depth']}, "
                 f"resumes/request {r['resumes_per_request']:.3f}")
+    if args.growth > 0:
+        g = S.large_actions(seed=args.seed, n_plans=args.plans, n_requests=args.growth)
+        gctx = fm.context_for(g, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
+                              planner_threads=args.planner_threads)
+        gctx.snapshot()
+        gctx.set_proposal(fm.PROPOSE_MLP, args.top_k, net, args.refresh)
+        rate = args.serve_rate if args.serve_rate > 0 else 200.0
+        log(f"growth: {args.growth} arrivals at {rate:g} req/s from {g.plans.n} plans ...")
+        r = _serve(gctx, g, S, rate, args.growth)
+        r["plans_at_start"] = int(g.plans.n)
+        r["plans_at_end"] = int(gctx.n_plans)
+        out["growth"] = r
+        log(f"growth: {r['plans_at_start']} -> {r['plans_at_end']} plans, achieved {r['achieved_req_s']:.1f} req/s, "
+            f"p50 {r['p50_latency_ms']:.1f} ms, p99 {r['p99_latency_ms']:.1f} ms, queue mean "
+            f"{r['mean_queue_depth']:.2f} max {r['max_queue_depth']}, resumes/request {r['resumes_per_request']:.3f}")
+        gctx.close()
     ctx.close()
     net.close()
 
