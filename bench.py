@@ -69,8 +69,20 @@ def cpu_baseline(sc, budget_s: float):
             break
     el = time.perf_counter() - t0
     return {"value": n / el, "unit": "req/s", "cores": O.num_threads(), "kind": "oracle",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "build": "gcc -O3 -fopenmp, no fast-math",
             "sample": f"first {n} of the {sc.requests.n} FCFS requests (plan + commit, FP64, literal per-peak "
-                      f"maximum), {el:.1f} s"}
+                      f"maximum, OpenMP over the actions of a step), {el:.1f} s"}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _leg(ctx, reqs, mode, net, k, steps, warmup, name, refresh=1):

@@ -140,17 +140,56 @@ static int outside_box(const orc_config *c, const double p[3]) {
     return 0;
 }
 
-/* Forward projection of one action: heading offset 2*pi*h/H from the goal
- * bearing beta, horizontal speed v, climb rate c, for one step dt. */
-static void successor(const orc_config *c, const double s[3], double beta, int a, double out[3]) {
+/* Forward projection of one action held for w steps: heading offset
+ * 2*pi*h/H from the goal bearing beta, horizontal speed v, climb rate c,
+ * for w * dt ("Forward project" kernel; w = 1 is the successor). */
+static void window_point(const orc_config *c, const double s[3], double beta, int a, int w, double out[3]) {
     int v = a % c->n_speed;
     int cl = (a / c->n_speed) % c->n_climb;
     int h = a / (c->n_speed * c->n_climb);
     double th = beta + 2.0 * M_PI * (double)h / (double)c->n_head;
+    double k = (double)w;
     double step = c->speed[v] * c->dt;
-    out[0] = s[0] + step * cos(th);
-    out[1] = s[1] + step * sin(th);
-    out[2] = s[2] + c->climb[cl] * c->dt;
+    out[0] = s[0] + (k * step) * cos(th);
+    out[1] = s[1] + (k * step) * sin(th);
+    out[2] = s[2] + k * (c->climb[cl] * c->dt);
+}
+
+static void successor(const orc_config *c, const double s[3], double beta, int a, double out[3]) {
+    window_point(c, s, beta, a, 1, out);
+}
+
+static int window(const orc_config *c) { return c->lookahead > 1 ? c->lookahead : 1; }
+
+/* Intruder risk well at point p and row t: the largest [d < R] |r| gamma^(d/ell)
+ * over the plans active at row t, one peak per plan, evaluated literally.
+ * Also the nearest plan distance and whether any distance lies within the
+ * boundary band of the radius. */
+static double intruder_term(const orc_world *w, const double p[3], int32_t t, double *dnear, int *amb) {
+    const orc_config *c = &w->cfg;
+    double Ineg = 0.0, dn = INFINITY;
+    for (int j = 0; j < w->n_plans; ++j) {
+        double q[3];
+        if (!plan_point(&w->plans[j], t, q)) continue;
+        double d = dist3(p, q);
+        int in = d < c->R_intr;
+        double val = in ? fabs(c->r_intr) * pow(c->gamma_intr, d / w->ell) : 0.0;
+        if (val > Ineg) Ineg = val;
+        if (d < dn) dn = d;
+        if (fabs(d - c->R_intr) <= c->amb_band) *amb = 1;
+    }
+    *dnear = dn;
+    return Ineg;
+}
+
+/* Terrain clearance well at point p (0 without terrain). */
+static double terrain_term(const orc_world *w, const double p[3], int *amb) {
+    const orc_config *c = &w->cfg;
+    if (!w->terr) return 0.0;
+    double clr = p[2] - terrain_height(w, p[0], p[1]);
+    int in = clr < c->R_terr;
+    if (fabs(clr - c->R_terr) <= c->amb_band) *amb = 1;
+    return in ? fabs(c->r_terr) * pow(c->gamma_terr, (clr > 0.0 ? clr : 0.0) / w->ell) : 0.0;
 }
 
 static double goal_bearing(const double s[3], const double g[3]) {
@@ -185,45 +224,41 @@ int orc_eval_step(const orc_world *w, const double s[3], const double g[3], int3
 
 #pragma omp parallel for schedule(static)
     for (int a = 0; a < A; ++a) {
-        double sp[3];
-        successor(c, s, beta, a, sp);
+        double Vb = -INFINITY, Gb = 0.0, Ib = 0.0, Tb = 0.0, d1 = INFINITY;
+        int ambiguous = 0, inside1 = 1;
+        for (int k = 1; k <= window(c); ++k) {
+            double sp[3];
+            window_point(c, s, beta, a, k, sp);
 
-        /* positive peak: the goal */
-        double dg = dist3(g, sp);
-        double Gp = fabs(c->r_goal) * pow(c->gamma, dg / ell);
+            /* positive peak: the goal */
+            double dg = dist3(g, sp);
+            double Gp = fabs(c->r_goal) * pow(c->gamma, dg / ell);
 
-        /* negative peaks: one risk well per plan active at the successor's time */
-        double Ineg = 0.0, dnear = INFINITY;
-        int ambiguous = 0;
-        for (int j = 0; j < w->n_plans; ++j) {
-            double q[3];
-            if (!plan_point(&w->plans[j], t + 1, q)) continue;
-            double d = dist3(sp, q);
-            int in = d < c->R_intr;
-            double val = in ? fabs(c->r_intr) * pow(c->gamma_intr, d / ell) : 0.0;
-            if (val > Ineg) Ineg = val;
-            if (d < dnear) dnear = d;
-            if (fabs(d - c->R_intr) <= c->amb_band) ambiguous = 1;
+            /* negative peaks: one risk well per plan active at this point's
+             * time, and the terrain clearance well */
+            double dnear;
+            double Ineg = intruder_term(w, sp, t + k, &dnear, &ambiguous);
+            double Tneg = terrain_term(w, sp, &ambiguous);
+
+            double value = Gp - (Ineg > Tneg ? Ineg : Tneg);
+            if (outside_box(c, sp)) value = -INFINITY;
+            if (k == 1) {
+                d1 = dnear;
+                inside1 = value > -INFINITY;
+                Vb = value; Gb = Gp; Ib = Ineg; Tb = Tneg;
+            } else if (value > Vb) {
+                Vb = value; Gb = Gp; Ib = Ineg; Tb = Tneg;
+            }
         }
-
-        /* negative peak: terrain clearance well */
-        double Tneg = 0.0;
-        if (w->terr) {
-            double clr = sp[2] - terrain_height(w, sp[0], sp[1]);
-            int in = clr < c->R_terr;
-            Tneg = in ? fabs(c->r_terr) * pow(c->gamma_terr, (clr > 0.0 ? clr : 0.0) / ell) : 0.0;
-            if (fabs(clr - c->R_terr) <= c->amb_band) ambiguous = 1;
-        }
-
-        double value = Gp - (Ineg > Tneg ? Ineg : Tneg);
-        if (outside_box(c, sp)) value = -INFINITY;
+        /* the step itself must stay inside the box */
+        double value = inside1 ? Vb : -INFINITY;
 
         Vloc[a] = value;
         if (V) V[a] = value;
-        if (G) G[a] = Gp;
-        if (I) I[a] = Ineg;
-        if (T) T[a] = Tneg;
-        if (dmin) dmin[a] = dnear;
+        if (G) G[a] = Gb;
+        if (I) I[a] = Ib;
+        if (T) T[a] = Tb;
+        if (dmin) dmin[a] = d1;
         if (amb) amb[a] = ambiguous;
     }
     if (best) *best = select_action(Vloc, A, c->tie_rel);
@@ -277,8 +312,11 @@ int orc_plan(const orc_world *w, const double origin[3], const double goal[3], i
             act[n] = best; val[n] = V[best];
             n += 1;
             /* stop at the first collision: inside an intruder well means a
-             * plan closer than the separation radius at this time */
-            if (I[best] > 0.0) { st = ORC_REJECT_SEPARATION; break; }
+             * plan closer than the separation radius at this time (the
+             * chosen successor's own well, whatever the window scored) */
+            double dn;
+            int amb_unused = 0;
+            if (intruder_term(w, s, t, &dn, &amb_unused) > 0.0) { st = ORC_REJECT_SEPARATION; break; }
             if (w->terr && s[2] - terrain_height(w, s[0], s[1]) < 0.0) { st = ORC_REJECT_TERRAIN; break; }
         }
     }

@@ -26,7 +26,14 @@
  *   - distance in the discount exponent is measured in steps of
  *     ell = max_speed * dt metres;
  *   - one intruder peak per known plan, at that plan's own trajectory point
- *     at the successor's time; window W = 1;
+ *     at the time of the scored point;
+ *   - lookahead window of W steps (Alg. 1's one-step and ten-step forward
+ *     projections, "Forward project" and "Compute value" kernels): action a
+ *     held for w = 1..W steps reaches s + w * Delta_a at row t + w; its
+ *     value is the largest of the W point values (no floor at 0), -inf if
+ *     the first point leaves the box (window points outside it are left
+ *     out); the state advances by one step; W = 1 scores the successor
+ *     alone;
  *   - kinematic action model: heading offsets 2*pi*h/H from the goal bearing,
  *     climb rates and speeds from the config; action index a = (h*C + c)*S + v;
  *   - the airspace box is a hard mask (value -inf outside);
@@ -77,6 +84,7 @@ typedef struct {
     int32_t max_steps;
     double tie_rel;                       /* argmax tie band (relative)    */
     double amb_band;                      /* boundary-ambiguity band [m]   */
+    int32_t lookahead;                    /* window W >= 1 (0 reads as 1)  */
 } orc_config;
 
 typedef struct orc_world orc_world;
@@ -94,11 +102,14 @@ int  orc_num_threads(void);
 int  orc_set_terrain(orc_world *w, int32_t nx, int32_t ny, const float *h,
                      double x0, double y0, double cell);
 
-/* Score every action from state s at time row t against the plans active at
- * row t+1.  Outputs (length A each, any may be NULL): V value, G goal term,
- * I intruder term, T terrain term, dmin nearest-plan distance (inf if none),
- * amb 1 if a plan distance or the clearance lies within amb_band of its
- * radius.  *best = chosen action or -1 if every value is -inf. */
+/* Score every action from state s at time row t: its window points
+ * s + w * Delta_a against the plans active at row t + w, w = 1..W.
+ * Outputs (length A each, any may be NULL): V value (the window maximum),
+ * G goal term, I intruder term, T terrain term (the three at the window
+ * point that gives V, the first such; at the first point when V = -inf),
+ * dmin nearest-plan distance of the first point (inf if none), amb 1 if a
+ * plan distance or a clearance of any window point lies within amb_band of
+ * its radius.  *best = chosen action or -1 if every value is -inf. */
 int  orc_eval_step(const orc_world *w, const double s[3], const double g[3], int32_t t,
                    double *V, double *G, double *I, double *T, double *dmin,
                    int32_t *amb, int32_t *best);

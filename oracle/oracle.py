@@ -23,8 +23,8 @@ AMB_BAND = 1e-3       # metres: a distance this close to a radius is boundary-am
 
 
 def build(openmp: bool = True) -> str:
-    """Compile the oracle (plain C, -O2, no fast-math) into liboracle.so."""
-    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-Wall", "-Wextra",
+    """Compile the oracle (plain C, -O3, no fast-math) into liboracle.so."""
+    cmd = ["gcc", "-O3", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-Wall", "-Wextra",
            "-fno-fast-math", SRC, "-o", LIB + ".tmp", "-lm"]
     if openmp:
         cmd.insert(1, "-fopenmp")
@@ -46,6 +46,7 @@ class _Cfg(C.Structure):
         ("max_steps", C.c_int32),
         ("tie_rel", C.c_double),
         ("amb_band", C.c_double),
+        ("lookahead", C.c_int32),
     ]
 
 
@@ -107,6 +108,7 @@ def make_cfg(cfg) -> _Cfg:
     c.max_steps = int(cfg.max_steps)
     c.tie_rel = float(getattr(cfg, "tie_rel", TIE_REL))
     c.amb_band = float(getattr(cfg, "amb_band", AMB_BAND))
+    c.lookahead = int(getattr(cfg, "lookahead", 1))
     return c
 
 

@@ -54,6 +54,7 @@ class Config:
     max_steps: int = 3600        # steps per request (trajectory <= max_steps+1 points)
     plan_capacity: int = 4096    # plans per time row
     max_rows: int = 3601         # time rows in the table
+    lookahead: int = 1           # steps W of the scoring window (Alg. 1 forward projections)
 
     @property
     def n_climb(self) -> int:

@@ -81,6 +81,104 @@ def compare_trajectory(gp, op, orc, goal, pos_tol=1e-6, rel=REL_TOL):
     return n, False
 
 
+def classify_trajectory(gp, op, orc, goal, pos_tol=1e-6, rel=REL_TOL):
+    """Compare a GPU trajectory with the oracle's; never silent on a real mismatch.
+
+    Returns a dict: kind 'identical' (same status, points within pos_tol,
+    actions equal, values within rel), or an excused divergence at step
+    `at` -- 'near_tie' (the oracle's two best values at the diverging state
+    lie within the value tolerance) or 'band' (the oracle's or the GPU's
+    choice has a plan distance or clearance within the boundary band); plus
+    the largest relative value error over the compared points.  Raises
+    AssertionError on any other difference.
+    """
+    n = min(gp.n_points, op.n_points)
+    ga, oa = gp.actions(), op.action
+    gx, gv = gp.points(), gp.values()
+    mx = 0.0
+    for k in range(n):
+        assert np.max(np.abs(gx[k] - op.xyz[k])) <= pos_tol, f"point {k} differs"
+        if k > 0:
+            e = abs(gv[k] - op.value[k]) / max(abs(op.value[k]), 1e-300)
+            if e > rel:
+                assert _value_band(orc, op, goal, k), f"value at point {k}: rel error {e:.3e}"
+            else:
+                mx = max(mx, e)
+        if k + 1 < n and ga[k + 1] != oa[k + 1]:
+            o = orc.eval_step(op.xyz[k], goal, op.t0 + k)
+            v = np.where(np.isfinite(o["V"]), o["V"], -np.inf)
+            top = np.sort(v)[::-1]
+            near_tie = top.size > 1 and (top[0] - top[1]) <= rel * scale(o).max()
+            in_band = bool(o["amb"][oa[k + 1]]) or bool(o["amb"][ga[k + 1]])
+            assert near_tie or in_band, f"action at point {k + 1}: gpu {ga[k + 1]} oracle {oa[k + 1]}"
+            return dict(kind="near_tie" if near_tie else "band", at=k + 1, max_rel=mx)
+    assert gp.n_points == op.n_points, f"length {gp.n_points} vs {op.n_points}"
+    assert gp.status == op.status, f"status {gp.status} vs {op.status}"
+    return dict(kind="identical", at=-1, max_rel=mx)
+
+
 def _value_band(orc, op, goal, k):
     o = orc.eval_step(op.xyz[k - 1], goal, op.t0 + k - 1)
     return bool(o["amb"][op.action[k]])
+
+
+# ---------------------------------------------------------------------------
+# Separation invariant of the stored table (Sec. V: only collision-free plans
+# are accepted).  A plan is validated as planned (FP64) against the earlier
+# plans as stored (FP32) and then stored rounded to FP32.  Rounding moves a
+# point by at most half an FP32 spacing per axis, so any two stored points
+# at a common row, one of them from an accepted plan, are at least
+# R_sep - delta apart, with delta the length of that per-axis bound at the
+# box's largest coordinates.
+# ---------------------------------------------------------------------------
+
+def fp32_rounding_bound(box_min, box_max) -> float:
+    """Largest distance between an FP64 point of the box and its FP32 rounding."""
+    m = np.maximum(np.abs(np.asarray(box_min, np.float64)), np.abs(np.asarray(box_max, np.float64)))
+    half = np.spacing(m.astype(np.float32)).astype(np.float64) / 2.0
+    return float(np.sqrt(np.sum(half * half)))
+
+
+def separation_report(known, accepted, R_sep, delta, probe=50.0):
+    """Stored-versus-stored separation over every row.
+
+    known: [(t0, points)] loaded plans (their mutual distances are not
+    checked: they were never validated); accepted: [(t0, points)] accepted
+    plans as stored (FP32 values), in acceptance order.  Returns the number
+    of pairs closer than R_sep - delta and the smallest distance of a pair
+    involving an accepted plan (inf when none is within R_sep + probe).
+    """
+    from scipy.spatial import cKDTree
+    R, P, T = [], [], []
+    for tag, plans in ((0, known), (1, accepted)):
+        for t0, x in plans:
+            x = np.asarray(x, np.float64).reshape(-1, 3)
+            R.append(int(t0) + np.arange(x.shape[0]))
+            P.append(x)
+            T.append(np.full(x.shape[0], tag, np.int8))
+    if not R:
+        return 0, np.inf
+    R, P, T = np.concatenate(R), np.concatenate(P), np.concatenate(T)
+    order = np.argsort(R, kind="stable")
+    R, P, T = R[order], P[order], T[order]
+    cuts = np.flatnonzero(np.diff(R)) + 1
+    rows = zip(np.split(P, cuts), np.split(T, cuts))
+    gap, bad = np.inf, 0
+    for pts, tags in rows:
+        if not tags.any() or len(tags) < 2:
+            continue
+        pairs = cKDTree(pts).query_pairs(R_sep + probe, output_type="ndarray")
+        if pairs.size == 0:
+            continue
+        pairs = pairs[(tags[pairs[:, 0]] == 1) | (tags[pairs[:, 1]] == 1)]
+        if pairs.size == 0:
+            continue
+        d = np.linalg.norm(pts[pairs[:, 0]] - pts[pairs[:, 1]], axis=1)
+        gap = min(gap, float(d.min()))
+        bad += int(np.sum(d < R_sep - delta))
+    return bad, gap
+
+
+def stored(t0, xyz):
+    """An accepted plan as the table stores it (FP32 values)."""
+    return int(t0), np.asarray(xyz, np.float64).astype(np.float32).astype(np.float64)

@@ -9,6 +9,7 @@ formulation (nearest-plan distance via a library distance routine).
 import json
 import math
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -17,6 +18,9 @@ from scipy.spatial.distance import cdist
 from oracle.oracle import Oracle, action_index, run_fcfs
 from oracle.vi import greedy_chain, value_iteration_chain
 from paper_2008_03518_amd import scenario as S
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from parity import fp32_rounding_bound, separation_report, stored  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -289,6 +293,44 @@ def test_terrain_plane_clearance():
     assert np.any(expect > 0) and np.any(expect == 0)
 
 
+# Terrain well constants (r_T, gamma_T, R_T) distinct from the intruder
+# well's (Sec. III: each negative peak carries its own reward, discount and
+# radius; "Process negative terrain rewards").  Hand values, 40 decimal
+# digits: 2.5 * 0.95^(55/40) = 2.329753462960785240871...,
+# 2.5 * 0.95^(60/40) = 2.314863656892128927874...,
+# 2.5 * 0.95^(65/40) = 2.300069013821741297421...
+TERRAIN_WELL_HAND = {55.0: 2.329753462960785240871, 60.0: 2.314863656892128927874,
+                     65.0: 2.300069013821741297421}
+
+
+def terrain_constants_cfg():
+    cfg = S.cfg_small()
+    cfg.r_terr, cfg.R_terr, cfg.gamma_terr = 2.5, 90.0, 0.95     # intruder well stays 1, 150 m, 0.99
+    return cfg
+
+
+def test_terrain_well_own_constants():
+    cfg = terrain_constants_cfg()
+    assert (cfg.r_intr, cfg.R_intr, cfg.gamma_intr) == (1.0, 150.0, 0.99)
+    ter = plane_terrain(0.0, 0.0, 40.0)                          # flat ground at 40 m
+    orc = Oracle(cfg, terrain=ter)
+    g = np.array([3000.0, 2000.0, 100.0])
+    # clearance 60 m at the state; climb rates -5, 0, +5 m/s over 1 s give
+    # clearances 55, 60, 65 m at every heading and speed (ell = 40 m)
+    r = orc.eval_step(np.array([3000.0, 7000.0, 100.0]), g, 0)
+    for a in range(cfg.n_actions):
+        clr = {0: 55.0, 1: 60.0, 2: 65.0}[(a // len(cfg.speed)) % len(cfg.climb)]
+        assert abs(r["T"][a] - TERRAIN_WELL_HAND[clr]) <= 1e-14 * TERRAIN_WELL_HAND[clr]
+        assert r["I"][a] == 0.0
+        assert r["V"][a] == r["G"][a] - r["T"][a]
+    # clearances 125-135 m: outside R_T = 90 m (inside the intruder radius 150 m)
+    r = orc.eval_step(np.array([3000.0, 7000.0, 170.0]), g, 0)
+    assert np.all(r["T"] == 0.0)
+    # below the surface: the well's full magnitude r_T (gamma_T^0)
+    r = orc.eval_step(np.array([3000.0, 7000.0, 38.0]), g, 0)
+    assert np.all(r["T"][[a for a in range(cfg.n_actions) if (a // 3) % 3 == 1]] == 2.5)
+
+
 def test_value_subtracts_larger_penalty():
     cfg = S.cfg_small()
     ter = plane_terrain(0.0, 0.0, 400.0)
@@ -369,21 +411,145 @@ def test_commit_validates_and_appends():
 # Separation invariant over a first-come-first-served sequence.
 # ---------------------------------------------------------------------------
 def test_fcfs_separation_invariant():
+    """Stored versus stored: every pair of table points at a common row, one
+    of them from an accepted plan, is at least R_sep - delta apart, delta
+    the FP32 rounding bound of a stored point (the invariant the GPU suite
+    checks with the same function)."""
     sc = S.small(seed=3, n_plans=80, n_requests=12)
     cfg = sc.cfg
     orc = Oracle(cfg, sc.plans)
     res = run_fcfs(orc, sc.requests)
-    committed = [(p.t0, p.xyz.astype(np.float32).astype(np.float64)) for p, ok in res if ok]
+    committed = [stored(p.t0, p.xyz) for p, ok in res if ok]
     assert len(committed) >= 8
     off = sc.plans.offsets()
-    known = [(int(sc.plans.t0[j]), sc.plans.xyz[off[j]:off[j + 1]].astype(np.float64)) for j in range(sc.plans.n)]
-    for i, (ti, xi) in enumerate(committed):
-        for tj, xj in known + committed[:i]:
-            lo, hi = max(ti, tj), min(ti + len(xi), tj + len(xj))
-            if lo >= hi:
-                continue
-            d = np.linalg.norm(xi[lo - ti:hi - ti] - xj[lo - tj:hi - tj], axis=1)
-            assert d.min() >= cfg.R_sep
+    known = [(int(sc.plans.t0[j]), sc.plans.xyz[off[j]:off[j + 1]]) for j in range(sc.plans.n)]
+    delta = fp32_rounding_bound(cfg.box_min, cfg.box_max)
+    assert 0.0 < delta < 1e-3                      # half a spacing of 10 km in FP32, two axes
+    bad, gap = separation_report(known, committed, cfg.R_sep, delta)
+    print(f"[separation] minimum stored gap {gap:.4f} m (bound {cfg.R_sep - delta:.4f} m)")
+    assert bad == 0 and gap >= cfg.R_sep - delta
     # every rejection is a stated outcome
     for p, ok in res:
         assert ok == (p.status == 0)
+
+
+def test_separation_report_finds_planted_violation():
+    """The checker itself: a stored point moved to R_sep - 2 delta from a
+    known plan is reported; moving it to R_sep exactly is not."""
+    delta = fp32_rounding_bound((0, 0, 0), (10000.0, 10000.0, 1000.0))
+    a = np.array([[5000.0, 5000.0, 500.0]] * 3)
+    for shift, want in ((150.0 - 2 * delta, 1), (150.0, 0)):
+        b = a + [shift, 0.0, 0.0]
+        bad, gap = separation_report([(0, a)], [(0, b)], 150.0, delta)
+        assert bad == 3 * want and abs(gap - shift) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Lookahead window (Alg. 1: one-step and ten-step forward projections;
+# "Forward project": W future points per action; "Compute value": the
+# largest value along the window).  Hand values, 30 digits:
+# 0.99^190.75 = 0.147032509431998899816819048270
+# 0.99^40 = 0.668971758569680513938338598804
+# 0.99^43 = 0.649102628368402432993856004081
+# ---------------------------------------------------------------------------
+def _window_cfg(W):
+    cfg = S.cfg_small()
+    cfg.lookahead = W
+    return cfg
+
+
+def test_lookahead_no_intruder_straight_value():
+    """No plans: the straight, level, fastest action's farthest window point
+    is W * ell nearer the goal, so its value is r * gamma^(D/ell - W), the
+    largest of all actions; the track stays straight while the goal is
+    farther than the window."""
+    cfg = _window_cfg(10)
+    orc = Oracle(cfg)
+    o, g = np.array([1000.0, 5000.0, 300.0]), np.array([9030.0, 5000.0, 300.0])   # D / ell = 200.75
+    r = orc.eval_step(o, g, 0)
+    straight = action_index(cfg, 0, 1, 2)
+    assert r["best"] == straight
+    assert abs(r["V"][straight] - 0.147032509431998899816819048270) <= 1e-14
+    p = orc.plan(o, g, 0)
+    assert p.status == 0
+    far = p.xyz[: 180]                                   # the goal still beyond the window
+    assert np.all(p.action[1:180] == straight)
+    assert np.max(np.abs(far[:, 1] - 5000.0)) < 1e-9 and np.max(np.abs(far[:, 2] - 300.0)) < 1e-9
+    assert np.allclose(np.diff(far[:, 0]), cfg.ell, rtol=0, atol=1e-9)
+
+
+def test_lookahead_takes_the_window_maximum_at_its_own_rows():
+    """A plan that appears at (1400, 5000, 300) from row 8 on (before that it
+    is far away): the straight action's window points 1040 .. 1400 m meet it
+    at rows 8, 9, 10 only, so its value is the goal term at w = 7,
+    0.99^43 (scoring every point against row t+1 would give 0.99^40, against
+    row t+w-1 0.99^42).  Without the window the same action scores its
+    successor alone: 0.99^49."""
+    o, g = np.array([1000.0, 5000.0, 300.0]), np.array([3000.0, 5000.0, 300.0])   # D = 2000 m = 50 ell
+    rows = 40
+    x = np.repeat(np.array([[9000.0, 9000.0, 900.0]], np.float32), rows, axis=0)
+    x[8:] = [1400.0, 5000.0, 300.0]
+    plans = S.Plans(np.zeros(1, np.int32), np.array([rows], np.int32), x)
+    straight = action_index(S.cfg_small(), 0, 1, 2)
+    r = Oracle(_window_cfg(10), plans).eval_step(o, g, 0)
+    assert abs(r["V"][straight] - 0.649102628368402432993856004081) <= 1e-14
+    assert r["I"][straight] == 0.0 and r["T"][straight] == 0.0 and r["V"][straight] == r["G"][straight]
+    r1 = Oracle(_window_cfg(1), plans).eval_step(o, g, 0)
+    assert abs(r1["V"][straight] - 0.99 ** 49) <= 1e-15
+    # a plan parked 100 m ahead at every row: points w = 1..6 lie inside its
+    # well, w = 7..10 outside, so the value is the goal term at w = 10
+    parked_ahead = S.Plans(np.zeros(1, np.int32), np.array([rows], np.int32),
+                           np.repeat(np.array([[1100.0, 5000.0, 300.0]], np.float32), rows, axis=0))
+    r = Oracle(_window_cfg(10), parked_ahead).eval_step(o, g, 0)
+    assert abs(r["V"][straight] - 0.668971758569680513938338598804) <= 1e-14
+    # the chosen successor's own well decides a rejection, whatever the window
+    # scored: parked 175 m ahead (the origin clear of its well), the straight
+    # action still wins on its clear points w = 9, 10 and its successor lies
+    # 135 m from the plan
+    ahead175 = S.Plans(np.zeros(1, np.int32), np.array([rows], np.int32),
+                       np.repeat(np.array([[1175.0, 5000.0, 300.0]], np.float32), rows, axis=0))
+    orc = Oracle(_window_cfg(10), ahead175)
+    assert orc.eval_step(o, g, 0)["best"] == straight
+    p = orc.plan(o, g, 0)
+    assert p.status == 1 and p.n_points == 2 and p.action[1] == straight
+
+
+def test_lookahead_equals_nearest_plan_window_maximum():
+    """Second formulation: window points built here, nearest plan per row by
+    a library distance routine (the monotone well makes the per-peak maximum
+    the nearest plan's), maximum over the window."""
+    cfg = _window_cfg(6)
+    sc = S.small(seed=17, n_plans=150, n_requests=1)
+    orc = Oracle(cfg, sc.plans)
+    off = sc.plans.offsets()
+    rng = np.random.default_rng(5)
+    A = cfg.n_actions
+    for trial in range(6):
+        j = int(rng.integers(sc.plans.n))
+        t = int(rng.integers(0, max(1, int(sc.plans.length[j]) - 8)))
+        s = sc.plans.xyz[off[j] + t].astype(np.float64) + rng.uniform(-200, 200, 3) * [1, 1, 0.3]
+        s[2] = min(max(s[2], 50.0), 950.0)
+        g = np.array([rng.uniform(0, 10000), rng.uniform(0, 10000), rng.uniform(100, 900)])
+        r = orc.eval_step(s, g, t)
+        beta = math.atan2(g[1] - s[1], g[0] - s[0])
+        best = np.full(A, -np.inf)
+        for a in range(A):
+            h, c, v = a // 9, (a // 3) % 3, a % 3
+            th = beta + 2 * math.pi * h / cfg.n_head
+            for w in range(1, cfg.lookahead + 1):
+                p = s + w * np.array([cfg.speed[v] * cfg.dt * math.cos(th), cfg.speed[v] * cfg.dt * math.sin(th),
+                                      cfg.climb[c] * cfg.dt])
+                inside = np.all(p >= cfg.box_min) and np.all(p <= cfg.box_max)
+                if w == 1 and not inside:
+                    break
+                if not inside:
+                    continue
+                act = [k for k in range(sc.plans.n) if sc.plans.t0[k] <= t + w < sc.plans.t0[k] + sc.plans.length[k]]
+                pts = np.array([sc.plans.xyz[off[k] + t + w - sc.plans.t0[k]] for k in act], np.float64)
+                d = cdist(p[None, :], pts).min() if len(act) else np.inf
+                well = cfg.r_intr * cfg.gamma_intr ** (d / cfg.ell) if d < cfg.R_intr else 0.0
+                val = cfg.r_goal * cfg.gamma ** (np.linalg.norm(g - p) / cfg.ell) - well
+                best[a] = max(best[a], val)
+        fin = np.isfinite(best)
+        assert np.array_equal(fin, np.isfinite(r["V"]))
+        assert np.allclose(r["V"][fin], best[fin], rtol=1e-12, atol=1e-15)
