@@ -46,6 +46,8 @@ def _traffic(leg: str):
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2008_03518_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    if leg not in TRAFFIC_BYTES_PER_LAUNCH:
+        return None
     return TRAFFIC_BYTES_PER_LAUNCH[leg] if h.hexdigest() == TRAFFIC_SHA256 else None
 
 
@@ -251,6 +253,8 @@ def main():
     ap.add_argument("--sequential", type=int, default=0,
                     help="also plan the first N requests one at a time (plan, then commit) with the full "
                          "sweep and compare with the concurrent pass; 0 disables")
+    ap.add_argument("--lookahead", type=int, default=10,
+                    help="also time one FCFS pass with this scoring window W (full sweep); 0 or 1 disables")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work; 0 disables")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -360,6 +364,27 @@ def main():
         out["ablations"]["trained_network"] = {"value": prop["value"], "certified_step_rate": cert_rate(prop),
                                                "pair_evals": prop["pairs"] / len(prop["times"])}
         untrained.close()
+
+    if args.lookahead > 1:
+        import copy
+        lsc = copy.deepcopy(sc)
+        lsc.cfg.lookahead = args.lookahead
+        lctx = fm.context_for(lsc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
+                              planner_threads=args.planner_threads)
+        lctx.snapshot()
+        name = f"window {args.lookahead}"
+        r = _leg(lctx, reqs, fm.PROPOSE_NONE, None, args.top_k, 1, 1, name)
+        lst = np.array([p.status for p in r["plans"]])
+        out["lookahead"] = {
+            "window": args.lookahead, "value": r["value"], "ms_per_step": r["ms_per_step"],
+            "planner_steps": r["steps"], "pair_evals_per_s": r["pairs"] / (r["kms"] * 1e-3), "resumes": r["resumes"],
+            "committed_per_step": int(r["committed"].sum()),
+            "status_counts": {S.STATUS_NAMES[int(k)]: int((lst == k).sum()) for k in np.unique(lst)},
+            "roofline": _roofline(r, "lookahead"),
+        }
+        log(f"{name}: {r['value']:.0f} req/s, committed {int(r['committed'].sum())}/{reqs.n}, "
+            f"status {out['lookahead']['status_counts']}")
+        lctx.close()
 
     if args.sequential > 0:
         out["sequential_full_sweep"] = _sequential(ctx, reqs, min(args.sequential, reqs.n), full)

@@ -95,6 +95,18 @@ typedef struct {
                                         request per compute unit)                 */
     double tie_rel;                  /* argmax: values within tie_rel*|max| of the
                                         maximum tie; the lowest index wins        */
+    int32_t lookahead;               /* scoring window W, 1..16 (0 reads as 1):
+                                        action a held for w = 1..W steps reaches
+                                        s + w*Delta_a at row t+w, and its value is
+                                        the largest value along the window (Alg. 1
+                                        forward projections; "Forward project" and
+                                        "Compute value" kernels); -inf if the
+                                        successor (w = 1) leaves the box, window
+                                        points outside the box are left out.  The
+                                        state still advances one step, and a
+                                        successor inside an intruder well still
+                                        rejects.  W > 1 runs the full sweep at
+                                        every step (no proposal). */
 } fastmdp_config;
 
 /* A plan request: aircraft identifier, source and destination (Sec. I),
@@ -169,6 +181,20 @@ int fastmdp_eval_step(fastmdp_ctx *ctx, const fastmdp_state *state, double *valu
  * Errors: E_INVAL, E_CAPACITY, E_DEVICE. */
 int fastmdp_plan_request(fastmdp_ctx *ctx, const fastmdp_request *req, fastmdp_plan *out);
 
+/* Candidate departure times of one request (ground delay): the paper plans
+ * to generate candidate flight plans with different departure times and let
+ * the operator choose among the viable ones (Sec. V, scheduling at different
+ * departure times; "Expected Outcome").  The request is planned from each
+ * departure row t0[i], i < n, against the current table, all candidates at
+ * once (one workgroup each, all seeing the same table); nothing is
+ * committed.  plans[i] receives candidate i (buffers as for
+ * fastmdp_plan_request); *chosen is the index of the earliest departure whose
+ * plan reached the goal and passes the commit validation (the lowest index
+ * among equal rows), -1 if none.  1 <= n <= max_slots.
+ * Errors: E_INVAL, E_CAPACITY, E_DEVICE. */
+int fastmdp_plan_departures(fastmdp_ctx *ctx, const fastmdp_request *req, int32_t n, const int32_t *t0,
+                            fastmdp_plan *plans, int32_t *chosen);
+
 /* Accept a plan into the table (Sec. V: the accepted-plan database grows by
  * one trajectory).  The points are rounded to FP32 and re-validated against
  * every plan in the table (3-D distance >= R_sep at every shared row) and
@@ -196,7 +222,13 @@ int fastmdp_num_plans(const fastmdp_ctx *ctx);
  * trajectory (caller buffers as for fastmdp_plan_request); committed[i] is 1
  * if it entered the table; done_s[i] (may be NULL) is the time, in seconds
  * since the call started, at which request i was accepted or rejected.
- * Errors: E_INVAL, E_CAPACITY, E_DEVICE. */
+ * Errors: E_INVAL, E_CAPACITY (a row full, a trajectory past max_rows, the
+ * withdrawal log full), E_DEVICE.  A call that fails after admitting
+ * requests keeps the ones accepted so far: their plans stay in the table,
+ * visible to every later call, with plans[i] and committed[i] filled in;
+ * every entry of the other admitted requests is withdrawn and their
+ * committed[i] is 0, and the next call's requests follow the last accepted
+ * one in sequence. */
 int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, const double *arrival_s,
                       fastmdp_plan *plans, int32_t *committed, double *done_s);
 

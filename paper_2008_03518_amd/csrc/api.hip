@@ -108,7 +108,7 @@ void free_all(fastmdp_ctx *c) {
     hipFree(c->dTerr);
     hipFree(c->dSlots); hipFree(c->dList); hipFree(c->dOrder); hipFree(c->dNdone);
     hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen); hipFree(c->tr.top);
-    hipFree(c->tr.ep); hipFree(c->tr.col); hipFree(c->tr.nd);
+    hipFree(c->tr.ep); hipFree(c->tr.col); hipFree(c->tr.nd); hipFree(c->tr.seenw);
     hipFree(c->dEv); hipFree(c->dBest); hipFree(c->dPts); hipFree(c->dFlag);
     if (c->hSlots) hipHostFree(c->hSlots);
     if (c->hGather) hipHostFree(c->hGather);
@@ -138,6 +138,7 @@ int check_cfg(const fastmdp_config *c) {
         return FASTMDP_E_INVAL;
     if (!(c->tie_rel >= 0.0)) return FASTMDP_E_INVAL;
     if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads) return FASTMDP_E_INVAL;
+    if (c->lookahead < 0 || c->lookahead > fmdp::kMaxLookahead) return FASTMDP_E_INVAL;
     return 0;
 }
 
@@ -180,6 +181,8 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     const int mid = c.n_climb / 2;
     d.zero_climb = (c.climb[mid] == 0.0) ? mid : -1;
     d.max_steps = c.max_steps;
+    d.lookahead = c.lookahead > 1 ? c.lookahead : 1;
+    d.max_step = std::sqrt(vmax * vmax + cmax * cmax) * c.dt;
 }
 
 // Adds the last planner launch's duration (its events have completed).
@@ -355,6 +358,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->tr.ep, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.col, ssz);
     rc = rc ? rc : dev_alloc(&c->tr.nd, ssz);
+    if (c->dc.lookahead > 1) rc = rc ? rc : dev_alloc(&c->tr.seenw, ssz * c->dc.lookahead);
     c->dl_cap = 1 << 22;
     c->dl_start_cap = 1 << 20;             // one epoch per acceptance round
     rc = rc ? rc : dev_alloc(&c->dDlRow, (size_t)c->dl_cap);
@@ -545,6 +549,43 @@ int fastmdp_plan_request(fastmdp_ctx *ctx, const fastmdp_request *req, fastmdp_p
     return 0;
 }
 
+int fastmdp_plan_departures(fastmdp_ctx *ctx, const fastmdp_request *req, int32_t n, const int32_t *t0,
+                            fastmdp_plan *plans, int32_t *chosen) {
+    if (!ctx || !req || n < 1 || !t0 || !plans || !chosen) return FASTMDP_E_INVAL;
+    if (n > ctx->max_slots) return FASTMDP_E_CAPACITY;
+    for (int i = 0; i < n; ++i) {
+        if (t0[i] < 0) return FASTMDP_E_INVAL;
+        if (plans[i].capacity < ctx->stride || !plans[i].xyz || !plans[i].action || !plans[i].value)
+            return FASTMDP_E_CAPACITY;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    reset_stats(ctx);
+    Slot *hs = ctx->hSlots;
+    for (int i = 0; i < n; ++i) {
+        fastmdp_request r = *req;
+        r.t0 = t0[i];
+        hs[i] = fresh_slot(r, i, ctx->seq);            // every candidate sees the same table
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, n * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+    EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = timed_planner(ctx, n, nullptr, ctx->cfg.max_steps + 1, 1, 0, none);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, n * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    int best = -1;
+    for (int i = 0; i < n; ++i) {
+        rc = copy_plan_out(ctx, i, hs[i], &plans[i]);
+        if (rc) return rc;
+        ctx->st_pairs += hs[i].pairs;
+        ctx->st_steps += hs[i].steps;
+        // the earliest departure whose plan reached the goal and would be accepted
+        if (hs[i].status == FASTMDP_OK && hs[i].valid && (best < 0 || t0[i] < t0[best])) best = i;
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *chosen = best;
+    return 0;
+}
+
 int fastmdp_commit_plan(fastmdp_ctx *ctx, const fastmdp_plan *plan) {
     if (!ctx || !plan || !plan->xyz || plan->n_points < 1 || plan->t0 < 0) return FASTMDP_E_INVAL;
     if (plan->status != FASTMDP_OK) return FASTMDP_E_INVAL;
@@ -607,121 +648,144 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             return FASTMDP_E_DEVICE;
         return rc;
     };
-    while (next_commit < n) {
-        // admit arrived requests into free slots, in request order
-        bool dirty = false;
-        const double t_now = arrival_s ? now_s() : 0.0;
-        for (int s = 0; s < S && next_req < n; ++s)
-            if (slot_req[s] < 0) {
-                if (arrival_s && arrival_s[next_req] > t_now) break;
-                hs[s] = fresh_slot(reqs[next_req], next_req, seq0 + next_req);
-                slot_req[s] = next_req;
-                req_slot[next_req] = s;
-                ++next_req;
-                dirty = true;
+    auto run = [&]() -> int {
+        while (next_commit < n) {
+            // admit arrived requests into free slots, in request order
+            bool dirty = false;
+            const double t_now = arrival_s ? now_s() : 0.0;
+            for (int s = 0; s < S && next_req < n; ++s)
+                if (slot_req[s] < 0) {
+                    if (arrival_s && arrival_s[next_req] > t_now) break;
+                    hs[s] = fresh_slot(reqs[next_req], next_req, seq0 + next_req);
+                    slot_req[s] = next_req;
+                    req_slot[next_req] = s;
+                    ++next_req;
+                    dirty = true;
+                }
+            if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+            // plan the oldest running requests, one per compute unit (the
+            // planner's workgroups take a CU each), for up to `budget` steps: a
+            // request that waits for the next launch plans against the plans its
+            // predecessors finish in this one instead of re-planning after them
+            list.clear();
+            for (int s = 0; s < S; ++s)
+                if (slot_req[s] >= 0 && hs[s].status == fmdp::kRunning) list.push_back(s);
+            if ((int)list.size() > ctx->n_cu) {
+                std::nth_element(list.begin(), list.begin() + ctx->n_cu, list.end(),
+                                 [&](int a, int b) { return hs[a].req < hs[b].req; });
+                list.resize(ctx->n_cu);
             }
-        if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
-        // plan the oldest running requests, one per compute unit (the
-        // planner's workgroups take a CU each), for up to `budget` steps: a
-        // request that waits for the next launch plans against the plans its
-        // predecessors finish in this one instead of re-planning after them
-        list.clear();
-        for (int s = 0; s < S; ++s)
-            if (slot_req[s] >= 0 && hs[s].status == fmdp::kRunning) list.push_back(s);
-        if ((int)list.size() > ctx->n_cu) {
-            std::nth_element(list.begin(), list.begin() + ctx->n_cu, list.end(),
-                             [&](int a, int b) { return hs[a].req < hs[b].req; });
-            list.resize(ctx->n_cu);
-        }
-        if (list.empty() && next_commit == next_req) {
-            // idle until the next arrival
-            const double wait = arrival_s[next_req] - now_s();
-            if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.001)));
-            continue;
-        }
-        // One synchronisation per round: the planner launch, the acceptance
-        // pass over every admitted, not yet accepted request (its kernels
-        // skip the ones still planning), the copy of the slots back, and the
-        // trajectories accepted in the previous round on their way to the
-        // caller's plans, all in stream order.
-        const bool planned = !list.empty();
-        if (planned) {
-            std::memcpy(ctx->hList, list.data(), list.size() * sizeof(int));
-            HIP_TRY(hipMemcpyAsync(ctx->dList, ctx->hList, list.size() * sizeof(int), hipMemcpyHostToDevice,
-                                   ctx->stream));
-            EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
-            // the launch ends once a quarter of its requests have finished:
-            // the others resume after the acceptance pass, with new requests
-            // in the freed compute units
-            const int stop_target = std::max(1, (int)list.size() / 4);
-            int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, epoch, none, stop_target, false);
-            if (rc) return finish(rc);
-        }
-        pass.clear();
-        for (int r = next_commit; r < next_req; ++r) pass.push_back(req_slot[r]);
-        epoch += 1;
-        if (epoch + 1 >= ctx->dl_start_cap) return finish(FASTMDP_E_CAPACITY);
-        dl_start.resize(epoch + 1);
-        dl_start[epoch] = dl_len;
-        ctx->hDl[0] = dl_len;
-        std::memcpy(ctx->hPass, pass.data(), pass.size() * sizeof(int));
-        HIP_TRY(hipMemcpyAsync(ctx->dDlStart + epoch, ctx->hDl, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(hipMemcpyAsync(ctx->dPass, ctx->hPass, pass.size() * sizeof(int), hipMemcpyHostToDevice,
-                               ctx->stream));
-        HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dPass, (int)pass.size(), ctx->tr, dl, epoch,
+            if (list.empty() && next_commit == next_req) {
+                // idle until the next arrival
+                const double wait = arrival_s[next_req] - now_s();
+                if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.001)));
+                continue;
+            }
+            // One synchronisation per round: the planner launch, the acceptance
+            // pass over every admitted, not yet accepted request (its kernels
+            // skip the ones still planning), the copy of the slots back, and the
+            // trajectories accepted in the previous round on their way to the
+            // caller's plans, all in stream order.
+            const bool planned = !list.empty();
+            if (planned) {
+                std::memcpy(ctx->hList, list.data(), list.size() * sizeof(int));
+                HIP_TRY(hipMemcpyAsync(ctx->dList, ctx->hList, list.size() * sizeof(int), hipMemcpyHostToDevice,
                                        ctx->stream));
-        HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(hipMemcpyAsync(ctx->hDl + 1, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        // the trajectories accepted last round were gathered ahead of this
-        // round's launch: hand them to the caller while the planner runs
+                EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
+                // the launch ends once a quarter of its requests have finished:
+                // the others resume after the acceptance pass, with new requests
+                // in the freed compute units
+                const int stop_target = std::max(1, (int)list.size() / 4);
+                int rc = timed_planner(ctx, (int)list.size(), ctx->dList, budget, 1, epoch, none, stop_target, false);
+                if (rc) return finish(rc);
+            }
+            pass.clear();
+            for (int r = next_commit; r < next_req; ++r) pass.push_back(req_slot[r]);
+            epoch += 1;
+            if (epoch + 1 >= ctx->dl_start_cap) return finish(FASTMDP_E_CAPACITY);
+            dl_start.resize(epoch + 1);
+            dl_start[epoch] = dl_len;
+            ctx->hDl[0] = dl_len;
+            std::memcpy(ctx->hPass, pass.data(), pass.size() * sizeof(int));
+            HIP_TRY(hipMemcpyAsync(ctx->dDlStart + epoch, ctx->hDl, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(ctx->dPass, ctx->hPass, pass.size() * sizeof(int), hipMemcpyHostToDevice,
+                                   ctx->stream));
+            HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dPass, (int)pass.size(), ctx->tr, dl, epoch,
+                                           ctx->stream));
+            HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(ctx->hDl + 1, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            // the trajectories accepted last round were gathered ahead of this
+            // round's launch: hand them to the caller while the planner runs
+            if (!pending.empty()) {
+                HIP_TRY(hipEventSynchronize(ctx->eGather));
+                gather_unpack(ctx, pending, plans);
+            }
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            dl_len = ctx->hDl[1];
+            if (planned) {
+                int rc = planner_time(ctx);
+                if (rc) return finish(rc);
+            }
+            if (dl_len > ctx->dl_cap) return finish(FASTMDP_E_CAPACITY);
+            for (int s : pass) {
+                if (hs[s].err) return finish(FASTMDP_E_CAPACITY);
+            }
+            // accept in request order: a finished request whose predecessors are
+            // all accepted is final; one that withdrew entries in this pass ends
+            // the walk (later requests are checked against it next pass)
+            const double t_done = now_s();
+            std::vector<int> acc_slots, acc_reqs;
+            while (next_commit < next_req) {
+                const int s = req_slot[next_commit];
+                if (hs[s].status == fmdp::kRunning) break;
+                const int r = next_commit;
+                committed[r] = (hs[s].status == FASTMDP_OK && hs[s].valid) ? 1 : 0;
+                if (done_s) done_s[r] = t_done;
+                ctx->n_plans += committed[r];
+                ctx->st_pairs += hs[s].pairs;
+                ctx->st_steps += hs[s].steps;
+                ctx->st_hit += hs[s].cert_hit;
+                ctx->st_miss += hs[s].cert_miss;
+                ctx->st_resumes += hs[s].resumes;
+                acc_slots.push_back(s);
+                acc_reqs.push_back(r);
+                ++next_commit;
+                if (hs[s].killed) break;
+            }
+            if (!acc_slots.empty()) {
+                int rc = gather_enqueue(ctx, acc_slots, acc_reqs, hs, plans, pending);
+                if (rc) return finish(rc);
+                for (int s : acc_slots) slot_req[s] = -1;   // reusable: the gather precedes any new planning
+            }
+        }
         if (!pending.empty()) {
-            HIP_TRY(hipEventSynchronize(ctx->eGather));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
             gather_unpack(ctx, pending, plans);
         }
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
-        dl_len = ctx->hDl[1];
-        if (planned) {
-            int rc = planner_time(ctx);
-            if (rc) return finish(rc);
-        }
-        if (dl_len > ctx->dl_cap) return finish(FASTMDP_E_CAPACITY);
-        for (int s : pass) {
-            if (hs[s].err) return finish(FASTMDP_E_CAPACITY);
-        }
-        // accept in request order: a finished request whose predecessors are
-        // all accepted is final; one that withdrew entries in this pass ends
-        // the walk (later requests are checked against it next pass)
-        const double t_done = now_s();
-        std::vector<int> acc_slots, acc_reqs;
-        while (next_commit < next_req) {
-            const int s = req_slot[next_commit];
-            if (hs[s].status == fmdp::kRunning) break;
-            const int r = next_commit;
-            committed[r] = (hs[s].status == FASTMDP_OK && hs[s].valid) ? 1 : 0;
-            if (done_s) done_s[r] = t_done;
-            ctx->n_plans += committed[r];
-            ctx->st_pairs += hs[s].pairs;
-            ctx->st_steps += hs[s].steps;
-            ctx->st_hit += hs[s].cert_hit;
-            ctx->st_miss += hs[s].cert_miss;
-            ctx->st_resumes += hs[s].resumes;
-            acc_slots.push_back(s);
-            acc_reqs.push_back(r);
-            ++next_commit;
-            if (hs[s].killed) break;
-        }
-        if (!acc_slots.empty()) {
-            int rc = gather_enqueue(ctx, acc_slots, acc_reqs, hs, plans, pending);
-            if (rc) return finish(rc);
-            for (int s : acc_slots) slot_req[s] = -1;   // reusable: the gather precedes any new planning
-        }
+        return 0;
+    };
+    const int rc = run();
+    if (rc == 0) {
+        ctx->seq = seq0 + n;
+        return finish(0);
     }
-    if (!pending.empty()) {
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
-        gather_unpack(ctx, pending, plans);
-    }
-    ctx->seq = seq0 + n;
-    return finish(0);
+    // An interrupted call keeps exactly the accepted requests: their plans
+    // stay in the table and are visible to every later request (sequence
+    // numbers below ctx->seq); the entries of every admitted request not yet
+    // accepted are withdrawn.  Accepted trajectories still on their way to
+    // the caller are delivered; committed[] is 0 from the first unaccepted
+    // request on.
+    hipStreamSynchronize(ctx->stream);
+    if (!pending.empty()) gather_unpack(ctx, pending, plans);
+    int m = 0;
+    for (int s = 0; s < S; ++s)
+        if (slot_req[s] >= 0) ctx->hPass[m++] = s;
+    if (m > 0 && hipMemcpyAsync(ctx->dPass, ctx->hPass, m * sizeof(int), hipMemcpyHostToDevice, ctx->stream) == hipSuccess)
+        fmdp::launch_fcfs_abort(ctx->tb, ctx->dSlots, ctx->dPass, m, ctx->tr, seq0 + next_commit, epoch + 1,
+                                ctx->stream);
+    for (int r = next_commit; r < n; ++r) committed[r] = 0;
+    ctx->seq = seq0 + next_commit;
+    return finish(rc);
 }
 
 int fastmdp_table_snapshot(fastmdp_ctx *ctx) {
@@ -778,6 +842,7 @@ int fastmdp_set_proposal(fastmdp_ctx *ctx, int32_t mode, int32_t top_k, int32_t 
     if (mode == FASTMDP_PROPOSE_NONE) {
         p.k = 0;
     } else if (mode == FASTMDP_PROPOSE_MLP || mode == FASTMDP_PROPOSE_GOAL) {
+        if (ctx->dc.lookahead > 1) return FASTMDP_E_INVAL;      // the window runs the full sweep
         if (top_k < 1 || top_k > FASTMDP_MAX_TOPK || top_k > ctx->A) return FASTMDP_E_INVAL;
         if (mode == FASTMDP_PROPOSE_MLP) {
             if (fmdp::mlp_weights(net, &p.net)) return FASTMDP_E_INVAL;

@@ -14,6 +14,7 @@ constexpr int kPropThreads = 512;   // with the proposal path: 8 wave64, twice t
 constexpr int kMaxActions = 512;
 constexpr int kMaxPoints = 4 * 4096;  // trajectory points per request (the validation list reuses the tile)
 constexpr int kMaxHeads = 128;
+constexpr int kMaxLookahead = 16;   // longest scoring window W (steps)
 constexpr int kRunning = -1;        // slot status while a request is being planned
 constexpr int kAlive = 0x7fffffff;  // table entry death epoch of a live entry
 constexpr double kBand = 1e-3;      // metres: FP32 nearest distances this close to the well
@@ -40,6 +41,9 @@ struct DevCfg {
     int n_head, n_climb, n_speed, n_actions;
     int zero_climb;                      // index of the zero climb rate in the middle, else -1
     int max_steps;
+    int lookahead;                       // scoring window W >= 1 (Alg. 1 forward projections)
+    double max_step;                     // longest action step [m]: window point w lies within
+                                         // w * max_step of the state
 };
 
 // Time-major structure-of-arrays known-plan table.  Entry j of row t is at
@@ -97,6 +101,8 @@ struct Traj {
     int *col;
     double *nd;      // squared distance from point k to the nearest plan of its row, as scored
                      // (infinity for the origin, which the origin check validated exactly)
+    int *seenw;      // window W > 1: seenw[k * W + w - 1] is the number of entries of row
+                     // t0 + k - 1 + w scored for window point w of the step to point k
     int stride;
 };
 
@@ -184,5 +190,9 @@ hipError_t launch_gather_traj(const Slot *slots, const int *list, int n_list, co
 // tentative insert, interaction check, withdrawal (see table.hip).
 hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, const int *list, int n_list,
                             const Traj &tr, const DeathLog &dl, int epoch, hipStream_t st);
+// Withdraw every table entry of the listed slots owned by sequence numbers
+// from min_own on (an interrupted FCFS call).
+hipError_t launch_fcfs_abort(const DevTable &t, Slot *slots, const int *list, int n_list, const Traj &tr, int min_own,
+                             int epoch, hipStream_t st);
 
 }  // namespace fmdp

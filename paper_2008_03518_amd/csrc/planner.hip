@@ -76,6 +76,18 @@ __device__ __forceinline__ void successor(const DevCfg &c, const ActTab &at, int
     z = s[2] + at.dz[cl];
 }
 
+// Point w of the lookahead window: action a held for w steps.
+__device__ __forceinline__ void window_point(const DevCfg &c, const ActTab &at, int a, int w, const double s[3],
+                                             double dx, double dy, double &x, double &y, double &z) {
+    const int v = a % c.n_speed;
+    const int cl = (a / c.n_speed) % c.n_climb;
+    const double k = (double)w;
+    const double step = k * at.step[v];
+    x = s[0] + step * dx;
+    y = s[1] + step * dy;
+    z = s[2] + k * at.dz[cl];
+}
+
 // Goal peak r_goal * gamma^(d/ell) at a successor.  Every action's value is
 // at most this term (the penalties are non-negative), the bound the
 // proposal certificate rests on; both use this one function.
@@ -96,9 +108,12 @@ __device__ __forceinline__ double nearest_d2(const ActTab &at, int a, float m) {
 // Score action a from state s: dx, dy is its heading's unit direction and
 // d2 the squared distance from the successor to the nearest plan.
 __device__ Scored score_action(const DevCfg &c, const DevTable &tb, const ActTab &at, int a, const double s[3],
-                               const double g[3], double dx, double dy, double d2) {
+                               const double g[3], double dx, double dy, double d2, int w = 0) {
     Scored r;
-    successor(c, at, a, s, dx, dy, r.x, r.y, r.z);
+    if (w > 0)
+        window_point(c, at, a, w, s, dx, dy, r.x, r.y, r.z);    // lookahead window point
+    else
+        successor(c, at, a, s, dx, dy, r.x, r.y, r.z);
     r.G = goal_term(c, r.x, r.y, r.z, g);
     r.I = 0.0;
     if (d2 < c.R_intr * c.R_intr) r.I = c.abs_r_intr * exp(c.log_gamma_intr * (sqrt(fmax(d2, 0.0)) / c.ell));
@@ -152,7 +167,7 @@ struct PlanGeom {
     static_assert(TILE % (4 * NT) == 0, "a chunk is a whole number of four-entry groups per thread");
 };
 
-template <int NT, int NC, int NV, int ZC, bool PROP>
+template <int NT, int NC, int NV, int ZC, bool PROP, bool LOOK = false>
 __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list,
                                                      Traj tr, int budget, int validate, int epoch, EvalOut ev,
                                                      PropArgs prop, LaunchStop stop) {
@@ -193,6 +208,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     // row entries seen, epoch, top action
     __shared__ double st_pv[5];
     __shared__ int st_pi[5], st_pend;
+    __shared__ int st_seenw[kMaxLookahead], st_pseenw[kMaxLookahead];   // window rows' entry counts:
+                                                                       // this step, the pending point
     __shared__ double sStep[FASTMDP_MAX_ACT_DIM], sDz[FASTMDP_MAX_ACT_DIM];   // speed*dt, climb*dt
     __shared__ float sKv[FASTMDP_MAX_ACT_DIM], sClf[FASTMDP_MAX_ACT_DIM];      // FP32 sweep constants
     const ActTab at{sStep, sDz};
@@ -284,13 +301,13 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     // issue the next row's loads as soon as it has staged this one.  The
     // first chunk of the next step's row is in flight during the sweep.
     int pre_n = 0, pre_lim = 0;
-    auto load_chunk = [&](int row, int base) {
+    auto load_chunk = [&](int row, int base, bool with_count = true) {
         const size_t rb = (size_t)row * tb.cap + base;
         const int lim = min(pre_n - base, tcap);
         pre_lim = lim;
         // the entry count of the following row travels with the first chunk,
         // so that the step does not wait for it on its own
-        if (base == 0 && tid == 0) {
+        if (base == 0 && tid == 0 && with_count) {
             if (row + 1 < tb.rows)
                 __builtin_amdgcn_global_load_lds(tb.rowN + row + 1, sNextN + ((row + 1) & 1), 4, 0, 0);
             else
@@ -390,7 +407,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     // Actions whose FP32 nearest distance lies within kBand of the well
     // radius (flagged in sBand) get it recomputed exactly in FP64 over the
     // visible entries of the row.  Uniform: every thread calls it.
-    auto band_recheck = [&](const double s[3], int n_row, size_t rb) {
+    auto band_recheck = [&](const double s[3], int n_row, size_t rb, int win = 0) {
         for (int w = 0; w < (A + 31) / 32; ++w) {
             unsigned bits = sBand[w];
             while (bits) {
@@ -398,7 +415,10 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 bits &= bits - 1;
                 const int h = a / (NC * NV);
                 double qx, qy, qz;
-                successor(cfg, at, a, s, sCos[h], sSin[h], qx, qy, qz);
+                if (win > 0)
+                    window_point(cfg, at, a, win, s, sCos[h], sSin[h], qx, qy, qz);
+                else
+                    successor(cfg, at, a, s, sCos[h], sSin[h], qx, qy, qz);
                 double dmin = INFINITY;
                 for (int j = tid; j < n_row; j += NT)
                     if (entry_visible(tb, rb + j, seq))
@@ -434,6 +454,9 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         tr.ep[p] = st_pi[3];
         tr.top[p] = st_pi[4];
         tr.col[p] = -1;
+        if constexpr (LOOK) {
+            for (int w = 0; w < cfg.lookahead; ++w) tr.seenw[p * cfg.lookahead + w] = st_pseenw[w];
+        }
         st_pend = 0;
     };
 
@@ -862,7 +885,173 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             else if (r.clr < 0.0) st_status = FASTMDP_REJECT_TERRAIN;
         };
 
-        if (!cert) {
+        if constexpr (LOOK) {
+            // Lookahead window (Alg. 1's forward projections; "Forward
+            // project": W points per action; "Compute value": the largest
+            // value along them).  Point w of action a is s + w * Delta_a,
+            // scored against row t + w: the same staging and sweep with the
+            // action constants scaled by w (|q - w Delta|^2 - w^2 |Delta|^2 =
+            // |q|^2 + w * (-2 Delta . q)).  Thread a keeps action a's running
+            // maximum; its successor (w = 1) decides the advance, the recorded
+            // nearest distance and the rejections.
+            const int W = cfg.lookahead;
+            const int a = tid;                                   // A <= kMaxActions <= NT
+            Scored r1{}, rbest{};
+            double vbest = -INFINITY, d2_1 = INFINITY;
+            float *red = reinterpret_cast<float *>(tile);
+            for (int w = 1; w <= W; ++w) {
+                const int roww = row + w - 1;                    // t + w
+                const int nw = w == 1 ? n_row : row_count(roww);
+                const size_t rbw = (size_t)roww * tb.cap;
+                const float fw = (float)w;
+                float ch = 0.0f, sh = 0.0f;
+                float kv[NV], clf[NC];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) kv[v] = fw * sKv[v];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) clf[c] = fw * sClf[c];
+                float acc[NC][NV];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[c][v] = INFINITY;
+                int nvis_w = 0;
+                for (int base = 0; base < nw; base += tcap) {
+                    if (w > 1 || base > 0) {                     // row t+1's first chunk came by prefetch
+                        lds_barrier();                           // the tile is free
+                        pre_n = nw;
+                        load_chunk(roww, base, false);
+                    }
+                    const int nv = stage_chunk(s);
+                    nvis_w += nv;
+                    lds_barrier();
+                    if (w == 1 && base == 0 && tid == 0) flush_point();
+                    if (base == 0 && sweeper) {
+                        ch = (float)sCos[my_h];
+                        sh = (float)sSin[my_h];
+                    }
+                    auto sweep2 = [&](const float4 p0, const float4 p1) {
+                        const float hq0 = fmaf(p0.x, ch, p0.y * sh);
+                        const float hq1 = fmaf(p1.x, ch, p1.y * sh);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const float u0 = fmaf(kv[v], hq0, p0.w);
+                            const float u1 = fmaf(kv[v], hq1, p1.w);
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) {
+                                const float a0 = (c == ZC) ? u0 : fmaf(clf[c], p0.z, u0);
+                                const float a1 = (c == ZC) ? u1 : fmaf(clf[c], p1.z, u1);
+                                acc[c][v] = fminf(acc[c][v], fminf(a0, a1));
+                            }
+                        }
+                    };
+                    const int full = (nv / (2 * n_slices)) * (2 * n_slices);
+                    if (sweeper) {
+                        for (int i = my_slice; i < full; i += 2 * n_slices) sweep2(tile[i], tile[i + n_slices]);
+                        if (full < nv) {
+                            const float4 far = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                            const int i = full + my_slice;
+                            sweep2(i < nv ? tile[i] : far, i + n_slices < nv ? tile[i + n_slices] : far);
+                        }
+                    }
+                }
+                if (tid == 0) {
+                    st_seenw[w - 1] = nw;
+                    pairs += (long long)A * nvis_w;
+                }
+                lds_barrier();                                   // the tile becomes the partials
+                if (sweeper) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) red[my_slice * A + (my_h * NC + c) * NV + v] = acc[c][v];
+                }
+                for (int q = tid; q < kMaxActions / 32; q += NT) sBand[q] = 0u;
+                lds_barrier();
+                bool myband = false;
+                if (a < A) {
+                    float m = INFINITY;
+                    for (int q = 0; q < n_part; ++q) m = fminf(m, red[q * A + a]);
+                    const double stepw = w * at.step[a % NV], dzw = w * at.dz[(a / NV) % NC];
+                    const double d2 = fma(dzw, dzw, fma(stepw, stepw, (double)m));
+                    sD2[a] = d2;
+                    if (d2 > cfg.band_lo2 && d2 < cfg.band_hi2) {
+                        atomicOr(&sBand[a >> 5], 1u << (a & 31));
+                        myband = true;
+                    }
+                }
+                if (myband) s_any = 1;
+                lds_barrier();
+                const int any_band = s_any;
+                if (any_band) {                                  // uniform; rare
+                    lds_barrier();                               // every thread has read the flag
+                    if (tid == 0) s_any = 0;
+                    band_recheck(s, nw, rbw, w);
+                }
+                if (a < A) {
+                    const int h = a / (NC * NV);
+                    const Scored rw = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a], w);
+                    if (w == 1) {
+                        r1 = rw;
+                        rbest = rw;
+                        vbest = rw.V;
+                        d2_1 = sD2[a];
+                    } else if (rw.V > vbest) {
+                        rbest = rw;
+                        vbest = rw.V;
+                    }
+                }
+                lds_barrier();                                   // partials and distances read
+            }
+            // the next step's first row (t + 2) while the argmax runs
+            if (!eval) {
+                pre_n = row_count(row + 1);
+                if (pre_n > 0) load_chunk(row + 1, 0, false);
+            }
+            const double myV = (a < A && r1.V > -INFINITY) ? vbest : -INFINITY;
+            const double wv = wave_max(myV);
+            if (lane == 0) red_d[wave] = wv;
+            lds_barrier();
+            double vm = -INFINITY;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) vm = fmax(vm, red_d[q]);
+            const double thr = vm - cfg.tie_rel * fabs(vm);
+            const int li = wave_min(a < A && myV >= thr ? a : 0x7fffffff);
+            const int ti = wave_min(a < A && myV == vm ? a : 0x7fffffff);
+            if (lane == 0) {
+                s_wli[wave] = li;
+                s_wti[wave] = ti;
+            }
+            if (eval && a < A) {
+                if (ev.V) ev.V[a] = myV;
+                if (ev.G) ev.G[a] = rbest.G;
+                if (ev.I) ev.I[a] = rbest.I;
+                if (ev.T) ev.T[a] = rbest.T;
+            }
+            lds_barrier();
+            int best = 0x7fffffff, top = 0x7fffffff;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                best = min(best, s_wli[q]);
+                top = min(top, s_wti[q]);
+            }
+            if (vm == -INFINITY) best = -1;
+            if (tid == 0) {
+                if (eval && ev.best) *ev.best = best;
+                if (!eval && best < 0) st_status = FASTMDP_NO_VALID_ACTION;
+                if (!eval && n_row == 0) take_stop();
+            }
+            if (!eval && best >= 0 && a == best) {
+                // the successor's scoring with the window's value
+                Scored adv = r1;
+                adv.V = myV;
+                sD2[best] = d2_1;
+                flush_point();                                   // the previous point keeps its counts
+                for (int q = 0; q < W; ++q) st_pseenw[q] = st_seenw[q];
+                advance(adv, best, top != best ? top : -1);
+            }
+        }
+        if (!LOOK && !cert) {
             // 2-3. stage (compacted) and sweep the row chunk by chunk: every
             //      lane, one heading's climb x speed actions over a slice of the
             //      staged plans (two plans per round: v_min3)
@@ -1141,7 +1330,10 @@ static hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, co
                            const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
                            const PropArgs &prop, const LaunchStop &stop) {
     (void)nt;
-    if (prop.mode == FASTMDP_PROPOSE_NONE)
+    if (c.lookahead > 1)
+        hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false, true>), dim3(nblk), dim3(kPlanThreads), 0,
+                           st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+    else if (prop.mode == FASTMDP_PROPOSE_NONE)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
                            t, s, list, tr, budget, validate, epoch, ev, prop, stop);
     else
@@ -1159,6 +1351,8 @@ hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, con
                           const PropArgs &prop, const LaunchStop &stop) {
     const int zc = c.zero_climb;
     if (prop.mode != FASTMDP_PROPOSE_NONE && (prop.k < 1 || prop.k > FASTMDP_MAX_TOPK || prop.k > c.n_actions))
+        return hipErrorInvalidValue;
+    if (c.lookahead > 1 && (prop.mode != FASTMDP_PROPOSE_NONE || c.lookahead > kMaxLookahead || !tr.seenw))
         return hipErrorInvalidValue;
     FMDP_SHAPE(1, 1, 0) FMDP_SHAPE(1, 1, -1) FMDP_SHAPE(1, 2, 0) FMDP_SHAPE(1, 2, -1)
     FMDP_SHAPE(1, 3, 0) FMDP_SHAPE(1, 3, -1)

@@ -266,6 +266,155 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
     }
 }
 
+// Lookahead window W > 1: the step to point k (from point k-1 at row
+// t0 + k - 1) scored rows t0 + k - 1 + w, w = 1..W, and recorded the entry
+// counts it saw in seenw.  The same two rules per window row: an added entry
+// matters within reach of the chosen action's window point w (or of the
+// largest action's, when the choice was made inside the tie band), a
+// withdrawn one within reach of any action's point w, i.e. within
+// reach + w * max_step of point k - 1.  The origin (k = 0) is the origin
+// check, as without the window.
+
+// Window point w of action a from state sp (the action's heading is an
+// offset from the goal bearing at sp).
+__device__ void table_window_point(const DevCfg &c, const double sp[3], const double goal[3], int a, int w,
+                                   double y[3]) {
+    const double bx = goal[0] - sp[0], by = goal[1] - sp[1];
+    const double r = sqrt(bx * bx + by * by);
+    const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
+    const int h = a / (c.n_climb * c.n_speed);
+    const int cl = (a / c.n_speed) % c.n_climb;
+    const int v = a % c.n_speed;
+    const double th = 2.0 * M_PI * (double)h / (double)c.n_head;
+    const double c0 = cos(th), s0 = sin(th);
+    const double k = (double)w;
+    const double step = k * (c.speed[v] * c.dt);
+    y[0] = sp[0] + step * (cb * c0 - sb * s0);
+    y[1] = sp[1] + step * (sb * c0 + cb * s0);
+    y[2] = sp[2] + k * (c.climb[cl] * c.dt);
+}
+
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_window_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                              const int *list, Traj tr, DeathLog dl,
+                                                                              int epoch) {
+    __shared__ int s_first, s_minep;
+    const int tid = threadIdx.x;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    if (S.status == kRunning) return;
+    const int n = S.n_points, t0 = S.t0, q = S.seq, W = c.lookahead;
+    const size_t base = (size_t)slot * tr.stride;
+    if (tid == 0) { s_first = 0x7fffffff; s_minep = 0x7fffffff; }
+    __syncthreads();
+    int mine = 0x7fffffff;
+    for (int k = tid; k < n; k += kPassThreads) mine = min(mine, tr.ep[base + k]);
+    atomicMin(&s_minep, mine);
+    __syncthreads();
+    const int minep = s_minep;
+    if (minep < epoch) {
+        const int lo = dl.start[minep + 1], hi = dl.start[epoch];
+        const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
+        for (int i = lo + blockIdx.y * kPassThreads + tid; i < hi; i += kPassThreads * kDeadSplit) {
+            const int row = dl.row[i], col = dl.col[i], e = dl.ep[i];
+            const size_t idx = (size_t)row * tb.cap + col;
+            if (tb.own[idx] >= q) continue;
+            const int r = row - t0;
+            if (r == 0 && n > 0 && col < tr.seen[base] && e > tr.ep[base]) {      // the origin check
+                const double *o = tr.xyz + base * 3;
+                if (entry_d2(o[0], o[1], o[2], tb.X[idx], tb.Y[idx], tb.Z[idx]) < ro2) atomicMin(&s_first, 0);
+            }
+            for (int w = 1; w <= W; ++w) {
+                const int k = r - w + 1;                  // the step to point k scored this row as point w
+                if (k < 1 || k >= n) continue;
+                if (col >= tr.seenw[(base + k) * W + w - 1] || e <= tr.ep[base + k]) continue;
+                const double *sp = tr.xyz + (base + k - 1) * 3;
+                const double rw = c.reach + w * c.max_step;
+                if (entry_d2(sp[0], sp[1], sp[2], tb.X[idx], tb.Y[idx], tb.Z[idx]) < rw * rw) atomicMin(&s_first, k);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && s_first != 0x7fffffff) atomicMin(&S.first, s_first);
+}
+
+// Added entries, window W > 1: one wave per point at a time, its lanes over
+// the new entries of each window row; the wave stops at the first entry in
+// reach.
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_add_window_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                             const int *list, Traj tr) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    if (S.status == kRunning) return;
+    const int n = S.n_points, t0 = S.t0, q = S.seq, W = c.lookahead;
+    const int k0 = blockIdx.y * kCheckPoints;
+    if (k0 >= n) return;
+    const size_t base = (size_t)slot * tr.stride;
+    const double r2 = c.reach * c.reach;
+    constexpr int per_wave = kCheckPoints / (kPassThreads / 64);
+    for (int i = 0; i < per_wave; ++i) {
+        const int k = k0 + wave * per_wave + i;
+        if (k >= n) break;
+        int hit = 0;
+        if (k == 0) {                                     // the origin check: row t0 against R_sep + 1 m
+            const int row = t0;
+            if (row < tb.rows) {
+                const int lo = tr.seen[base], hi = min(tb.rowN[row], tb.cap);
+                const double *x = tr.xyz + base * 3;
+                const size_t rb = (size_t)row * tb.cap;
+                for (int j = lo + lane; j < hi && !hit; j += 64)
+                    hit = entry_visible(tb, rb + j, q) &&
+                          entry_d2(x[0], x[1], x[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2;
+            }
+        } else {
+            const double *sp = tr.xyz + (base + k - 1) * 3, *sk = tr.xyz + (base + k) * 3;
+            const int top = tr.top[base + k];
+            for (int w = 1; w <= W && !__ballot(hit); ++w) {
+                const int row = t0 + k - 1 + w;
+                if (row >= tb.rows) break;
+                const int lo = tr.seenw[(base + k) * W + w - 1], hi = min(tb.rowN[row], tb.cap);
+                if (lo >= hi) continue;
+                // the chosen action's point w lies on the line through points k-1 and k
+                const double y[3] = {sp[0] + w * (sk[0] - sp[0]), sp[1] + w * (sk[1] - sp[1]),
+                                     sp[2] + w * (sk[2] - sp[2])};
+                double u[3] = {y[0], y[1], y[2]};
+                if (top >= 0) table_window_point(c, sp, S.goal, top, w, u);
+                const size_t rb = (size_t)row * tb.cap;
+                for (int j = lo + lane; j < hi && !hit; j += 64) {
+                    if (!entry_visible(tb, rb + j, q)) continue;
+                    const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
+                    hit = entry_d2(y[0], y[1], y[2], px, py, pz) < r2 || entry_d2(u[0], u[1], u[2], px, py, pz) < r2;
+                }
+            }
+        }
+        if (__ballot(hit)) {
+            if (lane == 0) atomicMin(&S.first, k);
+            break;                                        // later points of this wave cannot be first
+        }
+    }
+}
+
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_finish_window_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                                const int *list, Traj tr, int epoch) {
+    const int tid = threadIdx.x;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    if (S.status == kRunning) return;
+    const int n = S.n_points, t0 = S.t0, first = S.first, W = c.lookahead;
+    const size_t base = (size_t)slot * tr.stride;
+    for (int k = tid; k < min(n, first); k += kPassThreads) {
+        const int row = t0 + k;
+        if (row < tb.rows) tr.seen[base + k] = min(tb.rowN[row], tb.cap);
+        if (k > 0)
+            for (int w = 1; w <= W; ++w) {
+                const int rw = t0 + k - 1 + w;
+                tr.seenw[(base + k) * W + w - 1] = rw < tb.rows ? min(tb.rowN[rw], tb.cap) : 0;
+            }
+        tr.ep[base + k] = epoch - 1;
+    }
+    if (tid == 0) S.resume_at = first == 0x7fffffff ? -1 : first;
+}
+
 // Check, part 3 (one workgroup per request): steps before the first
 // affected one are consistent with the table now.
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_finish_kernel(DevTable tb, Slot *slots, const int *list,
@@ -330,6 +479,27 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_withdraw_kernel(DevTable tb
     }
 }
 
+// An interrupted call: every table entry of the listed slots (requests that
+// were admitted but not accepted) is withdrawn, whatever their state, so
+// that only accepted plans stay visible.  Only entries owned by sequence
+// numbers from min_own on (the unaccepted requests) are touched.
+__global__ __launch_bounds__(kPassThreads) void fcfs_abort_kernel(DevTable tb, Slot *slots, const int *list, Traj tr,
+                                                                  int min_own, int epoch) {
+    const int slot = list[blockIdx.x];
+    const Slot &S = slots[slot];
+    const int n = min(S.n_points, tr.stride), t0 = S.t0;
+    const size_t base = (size_t)slot * tr.stride;
+    for (int k = threadIdx.x; k < n; k += kPassThreads) {
+        const int col = tr.col[base + k];
+        const int row = t0 + k;
+        if (col < 0 || col >= tb.cap || row >= tb.rows) continue;
+        if (tb.own[(size_t)row * tb.cap + col] < min_own) continue;
+        tb.dead[(size_t)row * tb.cap + col] = epoch;
+        tb.vis[(size_t)row * tb.cap + col] = kAlive;
+        tr.col[base + k] = -1;
+    }
+}
+
 // Pack the trajectories of the listed slots into one buffer for a single
 // device-to-host copy: slot list[i]'s n_points points go to point offset
 // off[i]; xyz (3 doubles), then action, then value per point, in three
@@ -358,6 +528,13 @@ hipError_t launch_gather_traj(const Slot *slots, const int *list, int n_list, co
     double *val = xyz + 3 * total;
     int *act = reinterpret_cast<int *>(val + total);
     hipLaunchKernelGGL(gather_traj_kernel, dim3(n_list), dim3(256), 0, st, slots, list, off, total, tr, xyz, act, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcfs_abort(const DevTable &t, Slot *slots, const int *list, int n_list, const Traj &tr, int min_own,
+                             int epoch, hipStream_t st) {
+    if (n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fcfs_abort_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr, min_own, epoch);
     return hipGetLastError();
 }
 
@@ -392,11 +569,22 @@ hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, con
                             const Traj &tr, const DeathLog &dl, int epoch, hipStream_t st) {
     if (n_list <= 0) return hipSuccess;
     hipLaunchKernelGGL(fcfs_insert_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr);
-    hipLaunchKernelGGL(fcfs_check_dead_kernel, dim3(n_list, kDeadSplit), dim3(kPassThreads), 0, st, c, t, slots, list,
-                       tr, dl, epoch);
-    hipLaunchKernelGGL(fcfs_check_add_kernel, dim3(n_list, (tr.stride + kCheckPoints - 1) / kCheckPoints),
-                       dim3(kPassThreads), 0, st, c, t, slots, list, tr);
-    hipLaunchKernelGGL(fcfs_check_finish_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr, epoch);
+    if (c.lookahead > 1) {
+        if (!tr.seenw) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(fcfs_check_dead_window_kernel, dim3(n_list, kDeadSplit), dim3(kPassThreads), 0, st, c, t,
+                           slots, list, tr, dl, epoch);
+        hipLaunchKernelGGL(fcfs_check_add_window_kernel, dim3(n_list, (tr.stride + kCheckPoints - 1) / kCheckPoints),
+                           dim3(kPassThreads), 0, st, c, t, slots, list, tr);
+        hipLaunchKernelGGL(fcfs_check_finish_window_kernel, dim3(n_list), dim3(kPassThreads), 0, st, c, t, slots, list,
+                           tr, epoch);
+    } else {
+        hipLaunchKernelGGL(fcfs_check_dead_kernel, dim3(n_list, kDeadSplit), dim3(kPassThreads), 0, st, c, t, slots,
+                           list, tr, dl, epoch);
+        hipLaunchKernelGGL(fcfs_check_add_kernel, dim3(n_list, (tr.stride + kCheckPoints - 1) / kCheckPoints),
+                           dim3(kPassThreads), 0, st, c, t, slots, list, tr);
+        hipLaunchKernelGGL(fcfs_check_finish_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr,
+                           epoch);
+    }
     hipLaunchKernelGGL(fcfs_withdraw_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr, dl, epoch);
     return hipGetLastError();
 }

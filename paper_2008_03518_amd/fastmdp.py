@@ -48,6 +48,7 @@ class _Config(C.Structure):
         ("max_steps", C.c_int32), ("plan_capacity", C.c_int32), ("max_rows", C.c_int32),
         ("max_slots", C.c_int32), ("steps_per_launch", C.c_int32), ("planner_threads", C.c_int32),
         ("tie_rel", C.c_double),
+        ("lookahead", C.c_int32),
     ]
 
 
@@ -79,6 +80,7 @@ def _load_lib():
     lib.fastmdp_eval_step.argtypes = [P, C.POINTER(_State), dp, dp, dp, dp, ip]
     lib.fastmdp_plan_request.argtypes = [P, C.POINTER(_Request), C.POINTER(_Plan)]
     lib.fastmdp_commit_plan.argtypes = [P, C.POINTER(_Plan)]
+    lib.fastmdp_plan_departures.argtypes = [P, C.POINTER(_Request), I32, ip, C.POINTER(_Plan), ip]
     lib.fastmdp_num_plans.argtypes = [P]
     lib.fastmdp_plan_fcfs.argtypes = [P, I32, C.POINTER(_Request), dp, C.POINTER(_Plan), ip, dp]
     lib.fastmdp_table_snapshot.argtypes = [P]
@@ -117,7 +119,8 @@ _lib = _load_lib()
 
 EXPORTS = [
     "fastmdp_create", "fastmdp_destroy", "fastmdp_set_stream", "fastmdp_load_plans", "fastmdp_set_terrain",
-    "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_commit_plan", "fastmdp_num_plans", "fastmdp_plan_fcfs",
+    "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_plan_departures", "fastmdp_commit_plan",
+    "fastmdp_num_plans", "fastmdp_plan_fcfs",
     "fastmdp_last_stats", "fastmdp_save_table", "fastmdp_load_table", "fastmdp_strerror",
     "fastmdp_table_snapshot", "fastmdp_table_rewind",
     "fastmdp_mlp_create", "fastmdp_mlp_destroy", "fastmdp_mlp_num_params", "fastmdp_mlp_set_params",
@@ -255,6 +258,7 @@ def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_lau
     c.steps_per_launch = int(steps_per_launch)
     c.planner_threads = int(planner_threads)
     c.tie_rel = float(tie_rel)
+    c.lookahead = int(getattr(cfg, "lookahead", 1))
     return c
 
 
@@ -379,6 +383,24 @@ class Context:
         _check("fastmdp_plan_request", _lib.fastmdp_plan_request(self._h, C.byref(r), C.byref(p.c)))
         return p
 
+    def plan_departures(self, origin, goal, t0s, ident: int = 0):
+        """Plan one request from every departure row in t0s (nothing is
+        committed).  Returns (plans, chosen): chosen is the index of the
+        earliest departure whose plan would be accepted, -1 if none."""
+        t0s = np.ascontiguousarray(np.asarray(t0s, dtype=np.int32))
+        n = int(t0s.shape[0])
+        plans = [Plan(self.capacity) for _ in range(n)]
+        parr = (_Plan * max(n, 1))()
+        for k in range(n):
+            parr[k] = plans[k].c
+        r = _request(origin, goal, int(t0s[0]) if n else 0, ident)
+        chosen = np.zeros(1, dtype=np.int32)
+        _check("fastmdp_plan_departures", _lib.fastmdp_plan_departures(self._h, C.byref(r), n, _iptr(t0s), parr,
+                                                                       _iptr(chosen)))
+        for k in range(n):
+            plans[k].c = parr[k]
+        return plans, int(chosen[0])
+
     def commit_plan(self, plan: Plan) -> bool:
         """True if appended; False if refused for a separation/terrain conflict."""
         rc = _lib.fastmdp_commit_plan(self._h, C.byref(plan.c))
@@ -419,10 +441,15 @@ class Context:
         arr_s = None
         if arrival_s is not None:
             arr_s = np.ascontiguousarray(np.asarray(arrival_s, dtype=np.float64)[:m])
-        _check("fastmdp_plan_fcfs", _lib.fastmdp_plan_fcfs(self._h, m, arr, _dptr(arr_s) if arr_s is not None else None,
-                                                           parr, _iptr(committed), _dptr(done)))
+        rc = _lib.fastmdp_plan_fcfs(self._h, m, arr, _dptr(arr_s) if arr_s is not None else None, parr,
+                                    _iptr(committed), _dptr(done))
         for k in range(m):
             plans[k].c = parr[k]
+        if rc < 0:
+            # an interrupted call keeps the requests accepted before the error
+            err = FastMDPError("fastmdp_plan_fcfs", rc, strerror(rc))
+            err.plans, err.committed = plans, committed[:m].astype(bool)
+            raise err
         return plans, committed[:m].astype(bool), done[:m]
 
     def snapshot(self) -> None:

@@ -31,7 +31,7 @@ def compare_eval(g, o, rel=REL_TOL):
     assert np.array_equal(fin_o, fin_g), "box mask differs"
     sel = fin_o & ~band
     sc = scale(o)
-    err = np.abs(g["V"] - o["V"])[sel] / sc[sel]
+    err = np.abs(g["V"][sel] - o["V"][sel]) / sc[sel]
     mx = float(err.max()) if err.size else 0.0
     assert mx <= rel, f"value error {mx:.3e}"
     for key in ("G", "I", "T"):

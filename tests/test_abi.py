@@ -52,8 +52,8 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "fastmdp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(fastmdp_config), sizeof(fastmdp_request), sizeof(fastmdp_plan),
-         sizeof(fastmdp_state), offsetof(fastmdp_config, tie_rel));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(fastmdp_config), sizeof(fastmdp_request), sizeof(fastmdp_plan),
+         sizeof(fastmdp_state), offsetof(fastmdp_config, tie_rel), offsetof(fastmdp_config, lookahead));
   return 0;
 }
 '''
@@ -64,7 +64,7 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     got = [ctypes.sizeof(fm._Config), ctypes.sizeof(fm._Request), ctypes.sizeof(fm._Plan),
-           ctypes.sizeof(fm._State), fm._Config.tie_rel.offset]
+           ctypes.sizeof(fm._State), fm._Config.tie_rel.offset, fm._Config.lookahead.offset]
     assert [int(x) for x in out] == got
 
 
@@ -90,6 +90,8 @@ def test_create_rejects_invalid_configs():
     assert create(dt=0.0) == fm.E_INVAL
     assert create(max_steps=16383 + 1) == fm.E_INVAL
     assert create(max_rows=1) == fm.E_INVAL
+    assert create(lookahead=17) == fm.E_INVAL           # windows of at most 16 steps
+    assert create(lookahead=-1) == fm.E_INVAL
     assert fm._lib.fastmdp_create(None, ctypes.byref(out)) == fm.E_INVAL
 
 

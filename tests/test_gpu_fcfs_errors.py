@@ -33,7 +33,8 @@ def test_fcfs_error_keeps_accepted_plans(tmp_path):
     cfg = sc.cfg
     cfg.max_rows = 800
     reqs = sc.requests
-    reqs.t0[4] = 700                      # flies past row 799: its insertion fails
+    reqs.t0[4] = 790                      # flies past row 799 (about 38 steps): its insertion fails
+    assert np.linalg.norm(reqs.goal[4] - reqs.origin[4]) > 20 * cfg.ell
     arrival = np.array([0.0, 0.0, 0.0, 0.0, 0.5])   # admitted after the first four are accepted
     path = str(tmp_path / "t.bin")
     with fm.context_for(sc, max_slots=4) as ctx:

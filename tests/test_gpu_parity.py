@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from parity import compare_eval, compare_trajectory  # noqa: E402
+from parity import compare_eval, compare_trajectory, fp32_rounding_bound, separation_report, stored  # noqa: E402
 
 from oracle.oracle import Oracle  # noqa: E402
 from paper_2008_03518_amd import scenario as S  # noqa: E402
@@ -291,6 +291,31 @@ def test_planning_rows_beyond_one_tile(fm):
     _log(f"[rows beyond one tile] request 0: {op.n_points} points, identical {same}, diverged {diverged}")
 
 
+def test_terrain_well_own_constants(fm):
+    """Terrain well with r_T = 2.5, gamma_T = 0.95, R_T = 90 m (intruder
+    well 1, 0.99, 150 m) over flat ground at 40 m: per-action values against
+    the oracle, and the terrain term against the hand values the oracle's
+    pin uses (clearances 55 / 60 / 65 m by climb rate; none inside 90 m at
+    125-135 m; the full magnitude below the surface)."""
+    from test_oracle_pins import TERRAIN_WELL_HAND, plane_terrain, terrain_constants_cfg
+    cfg = terrain_constants_cfg()
+    ter = plane_terrain(0.0, 0.0, 40.0)
+    orc = Oracle(cfg, terrain=ter)
+    g = np.array([3000.0, 2000.0, 100.0])
+    with fm.Context(cfg) as ctx:
+        ctx.set_terrain(ter)
+        for z in (100.0, 170.0, 38.0):
+            s = np.array([3000.0, 7000.0, z])
+            r = ctx.eval_step(s, g, 0)
+            compare_eval(r, orc.eval_step(s, g, 0))
+            for a in range(cfg.n_actions):
+                c = (a // len(cfg.speed)) % len(cfg.climb)
+                clr = z - 40.0 + (c - 1) * 5.0
+                if clr in TERRAIN_WELL_HAND or clr >= cfg.R_terr or clr < 0:
+                    want = TERRAIN_WELL_HAND[clr] if clr in TERRAIN_WELL_HAND else (2.5 if clr < 0 else 0.0)
+                    assert abs(r["T"][a] - want) <= 1e-5 * max(want, 1e-300), (z, a, r["T"][a], want)
+
+
 def test_empty_table_straight_track(fm):
     cfg = S.cfg_large_actions()
     o, g = np.array([1000.0, 5000.0, 300.0]), np.array([9030.0, 5000.0, 300.0])
@@ -377,19 +402,16 @@ def test_determinism(fm):
 
 
 def _separation_violations(sc, plans, committed):
-    """Committed plans closer than R_sep to an earlier plan at a common row:
-    each plan's points as planned (FP64) against the earlier plans as the
-    table holds them (FP32), the comparison commit validation makes."""
+    """Stored-versus-stored separation of the accepted plans against the
+    known plans and each other: pairs closer than R_sep less the FP32
+    rounding bound of a stored point (the invariant the oracle suite checks
+    with the same function)."""
     off = sc.plans.offsets()
-    tabs = [(int(sc.plans.t0[j]), sc.plans.xyz[off[j]:off[j + 1]].astype(np.float64)) for j in range(sc.plans.n)]
-    bad = 0
-    mine = [(p.t0, p.points().copy()) for p, c in zip(plans, committed) if c]
-    stored = [(t, x.astype(np.float32).astype(np.float64)) for t, x in mine]
-    for i, (ti, xi) in enumerate(mine):
-        for tj, xj in tabs + stored[:i]:
-            lo, hi = max(ti, tj), min(ti + len(xi), tj + len(xj))
-            if lo < hi and np.min(np.linalg.norm(xi[lo - ti:hi - ti] - xj[lo - tj:hi - tj], axis=1)) < sc.cfg.R_sep:
-                bad += 1
+    known = [(int(sc.plans.t0[j]), sc.plans.xyz[off[j]:off[j + 1]]) for j in range(sc.plans.n)]
+    acc = [stored(p.t0, p.points()) for p, c in zip(plans, committed) if c]
+    delta = fp32_rounding_bound(sc.cfg.box_min, sc.cfg.box_max)
+    bad, gap = separation_report(known, acc, sc.cfg.R_sep, delta)
+    _log(f"[separation] {len(acc)} accepted plans, minimum stored gap {gap:.4f} m, bound {sc.cfg.R_sep - delta:.4f} m")
     return bad
 
 
