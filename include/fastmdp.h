@@ -158,6 +158,21 @@ int fastmdp_set_stream(fastmdp_ctx *ctx, void *hip_stream);
 int fastmdp_load_plans(fastmdp_ctx *ctx, int32_t n, const int32_t *t0, const int32_t *len,
                        const float *xyz);
 
+/* fastmdp_load_plans for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same arguments, result and table layout, but the plans travel through a
+ * fixed 8 MiB device staging array that the library holds on each GPU until
+ * the process ends, so the call makes no device or host allocation.  At most
+ * 65536 plans and 655360 points per call; larger loads return E_CAPACITY
+ * (split them over several calls).  Every context on one GPU shares that
+ * GPU's staging array: calls that overlap in time on one GPU (from several
+ * threads, on different contexts) race and must be serialised by the
+ * caller.  Errors: E_INVAL, E_CAPACITY (also: a row would exceed
+ * plan_capacity or a plan run past max_rows; the table is then unchanged),
+ * E_DEVICE. */
+int fastmdp_load_plans_noalloc(fastmdp_ctx *ctx, int32_t n, const int32_t *t0, const int32_t *len,
+                               const float *xyz);
+
 /* Terrain heightmap (the static terrain peaks of Sec. IV, "Build peaks"):
  * h[j*nx + i] is the height at (x0 + i*cell, y0 + j*cell); heights between
  * vertices are bilinear, positions outside the grid are clamped to its edge.

@@ -26,6 +26,40 @@ using fmdp::EvalOut;
 using fmdp::Slot;
 using fmdp::Traj;
 
+// Staging of fastmdp_load_plans_noalloc: a fixed device array, one copy on
+// every GPU the library runs on, held until the process ends.  Plan starts
+// and lengths take the first kNoallocPlanBytes, the FP32 points the rest.
+// Host code never passes `scratch` itself (its name is a host-side stand-in,
+// not a device address): it uses the address hipGetSymbolAddress returns on
+// each device (noalloc_scratch).
+constexpr int kNoallocMaxPlans = 65536;
+constexpr int kNoallocMaxPoints = 655360;
+constexpr size_t kNoallocPlanBytes = (size_t)2 * kNoallocMaxPlans * sizeof(int);
+constexpr size_t kNoallocBytes = kNoallocPlanBytes + (size_t)3 * kNoallocMaxPoints * sizeof(float);   // 8 MiB
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current), looked up once per
+// device.  nullptr if the lookup fails.
+void *noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            std::fprintf(stderr, "libfastmdp: hipGetSymbolAddress(scratch) failed on device %d\n", dev);
+            return nullptr;
+        }
+        g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
 struct fastmdp_ctx {
     fastmdp_config cfg{};
     DevCfg dc{};
@@ -40,6 +74,9 @@ struct fastmdp_ctx {
     float *dTerr = nullptr;
     int max_slots = 1, stride = 0;
     int n_cu = 256;                       // compute units of the device
+    int dev = 0;                          // HIP device of the context
+    void *dScratch = nullptr;             // this device's `scratch` (allocation-free plan loading)
+    std::vector<int> hRowTmp;             // row counts being checked by fastmdp_load_plans_noalloc
     Slot *dSlots = nullptr;
     int *dList = nullptr, *dOrder = nullptr, *dNdone = nullptr;
     Traj tr{};
@@ -403,11 +440,20 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     c->tr.stride = c->stride;
     {
         int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            c->n_cu = cus;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            c->dev = dev;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+                c->n_cu = cus;
+        }
+    }
+    c->dScratch = noalloc_scratch(c->dev);
+    if (!c->dScratch) {
+        free_all(c);
+        delete c;
+        return FASTMDP_E_DEVICE;
     }
     c->hRowN.assign(cfg->max_rows, 0);
+    c->hRowTmp.assign(cfg->max_rows, 0);
     if (fmdp::launch_fill_int(c->tb.rowN, 0, cfg->max_rows, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         free_all(c);
@@ -471,6 +517,44 @@ int fastmdp_load_plans(fastmdp_ctx *ctx, int32_t n, const int32_t *t0, const int
             std::fprintf(stderr, "libfastmdp: load_plans: %s\n", hipGetErrorString(e));
             return FASTMDP_E_DEVICE;
         }
+    }
+    ctx->hRowN.swap(rowN);
+    ctx->n_plans += n;
+    return 0;
+}
+
+int fastmdp_load_plans_noalloc(fastmdp_ctx *ctx, int32_t n, const int32_t *t0, const int32_t *len,
+                               const float *xyz) {
+    if (!ctx || n < 0 || (n > 0 && (!t0 || !len || !xyz))) return FASTMDP_E_INVAL;
+    if (n > kNoallocMaxPlans) return FASTMDP_E_CAPACITY;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    long long total = 0;
+    for (int j = 0; j < n; ++j) {
+        if (t0[j] < 0 || len[j] < 1) return FASTMDP_E_INVAL;
+        if ((long)t0[j] + len[j] > ctx->tb.rows) return FASTMDP_E_CAPACITY;
+        total += len[j];
+    }
+    if (total > kNoallocMaxPoints) return FASTMDP_E_CAPACITY;
+    if (n == 0) return 0;
+    // row counts after the load, in the context's own host buffer
+    std::vector<int> &rowN = ctx->hRowTmp;
+    std::copy(ctx->hRowN.begin(), ctx->hRowN.end(), rowN.begin());
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < len[j]; ++k)
+            if (++rowN[t0[j] + k] > ctx->tb.cap) return FASTMDP_E_CAPACITY;
+    unsigned char *base = static_cast<unsigned char *>(ctx->dScratch);
+    int *dT0 = reinterpret_cast<int *>(base);
+    int *dLen = dT0 + kNoallocMaxPlans;
+    float *dXyz = reinterpret_cast<float *>(base + kNoallocPlanBytes);
+    hipError_t e = hipMemcpyAsync(dT0, t0, (size_t)n * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dLen, len, (size_t)n * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dXyz, xyz, (size_t)total * 3 * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = fmdp::launch_append_plans(ctx->tb, dT0, dLen, n, dXyz, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "libfastmdp: load_plans_noalloc: %s\n", hipGetErrorString(e));
+        return FASTMDP_E_DEVICE;
     }
     ctx->hRowN.swap(rowN);
     ctx->n_plans += n;

@@ -178,6 +178,11 @@ int mlp_weights(const fastmdp_mlp *m, PropNet *w);
 hipError_t launch_fill_int(int *p, int value, int n, hipStream_t st);
 hipError_t launch_scatter_points(const DevTable &t, const float *pts, const int *rows, const int *cols, int n,
                                  int own, hipStream_t st);
+// Append n plans (t0[j], len[j], points plan-major in xyz; all device
+// pointers) in order, each row's entries in plan order; the caller has
+// checked rows and capacity.
+hipError_t launch_append_plans(const DevTable &t, const int *t0, const int *len, int n, const float *xyz,
+                               hipStream_t st);
 hipError_t launch_commit_check(const DevCfg &c, const DevTable &t, const double *pts, int t0, int n, int seq,
                                int *flag, hipStream_t st);
 hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, int n, int own, const int *flag,

@@ -43,6 +43,35 @@ __global__ void scatter_points_kernel(DevTable tb, const float *pts, const int *
     tb.dead[idx] = kAlive;
 }
 
+// Plans appended in order from one staging buffer, by one workgroup: plan j
+// (t0[j], len[j] points from xyz + 3 * off) takes the next column of each row
+// it spans.  A plan spans a row at most once, so its points take their
+// columns independently; plans follow one another behind a barrier, which
+// gives every row its entries in plan order (the columns the host-computed
+// scatter of fastmdp_load_plans gives).  The row counts move by device
+// atomics, which the next plan reads after the barrier.
+__global__ __launch_bounds__(1024) void append_plans_kernel(DevTable tb, const int *t0, const int *len, int n,
+                                                            const float *xyz) {
+    long long off = 0;
+    for (int j = 0; j < n; ++j) {
+        const int t = t0[j], L = len[j];
+        for (int k = threadIdx.x; k < L; k += blockDim.x) {
+            const int row = t + k;
+            const int col = atomicAdd(&tb.rowN[row], 1);
+            const size_t idx = (size_t)row * tb.cap + col;
+            const float *p = xyz + 3 * (off + k);
+            tb.X[idx] = p[0];
+            tb.Y[idx] = p[1];
+            tb.Z[idx] = p[2];
+            tb.vis[idx] = -1;
+            tb.own[idx] = -1;
+            tb.dead[idx] = kAlive;
+        }
+        off += L;
+        __syncthreads();
+    }
+}
+
 // Commit validation of one trajectory point as planned (FP64) against every
 // entry of its row visible to `seq`, as stored (FP32), in FP64; terrain
 // clearance; capacity.  flag bit 0: conflict, bit 1: capacity.
@@ -541,6 +570,13 @@ hipError_t launch_fcfs_abort(const DevTable &t, Slot *slots, const int *list, in
 hipError_t launch_fill_int(int *p, int value, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_append_plans(const DevTable &t, const int *t0, const int *len, int n, const float *xyz,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(append_plans_kernel, dim3(1), dim3(1024), 0, st, t, t0, len, n, xyz);
     return hipGetLastError();
 }
 

@@ -76,6 +76,7 @@ def _load_lib():
     lib.fastmdp_destroy.restype = None
     lib.fastmdp_set_stream.argtypes = [P, P]
     lib.fastmdp_load_plans.argtypes = [P, I32, ip, ip, fp]
+    lib.fastmdp_load_plans_noalloc.argtypes = [P, I32, ip, ip, fp]
     lib.fastmdp_set_terrain.argtypes = [P, I32, I32, fp, D, D, D]
     lib.fastmdp_eval_step.argtypes = [P, C.POINTER(_State), dp, dp, dp, dp, ip]
     lib.fastmdp_plan_request.argtypes = [P, C.POINTER(_Request), C.POINTER(_Plan)]
@@ -118,7 +119,8 @@ def _load_lib():
 _lib = _load_lib()
 
 EXPORTS = [
-    "fastmdp_create", "fastmdp_destroy", "fastmdp_set_stream", "fastmdp_load_plans", "fastmdp_set_terrain",
+    "fastmdp_create", "fastmdp_destroy", "fastmdp_set_stream", "fastmdp_load_plans", "fastmdp_load_plans_noalloc",
+    "fastmdp_set_terrain",
     "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_plan_departures", "fastmdp_commit_plan",
     "fastmdp_num_plans", "fastmdp_plan_fcfs",
     "fastmdp_last_stats", "fastmdp_save_table", "fastmdp_load_table", "fastmdp_strerror",
@@ -357,6 +359,14 @@ class Context:
         ln = np.ascontiguousarray(plans.length, dtype=np.int32)
         xyz = np.ascontiguousarray(plans.xyz, dtype=np.float32)
         _check("fastmdp_load_plans", _lib.fastmdp_load_plans(self._h, int(t0.shape[0]), _iptr(t0), _iptr(ln), _fptr(xyz)))
+
+    def load_plans_noalloc(self, plans) -> None:
+        """load_plans through the library's fixed staging array (no allocation)."""
+        t0 = np.ascontiguousarray(plans.t0, dtype=np.int32)
+        ln = np.ascontiguousarray(plans.length, dtype=np.int32)
+        xyz = np.ascontiguousarray(plans.xyz, dtype=np.float32)
+        _check("fastmdp_load_plans_noalloc",
+               _lib.fastmdp_load_plans_noalloc(self._h, int(t0.shape[0]), _iptr(t0), _iptr(ln), _fptr(xyz)))
 
     def set_terrain(self, terrain) -> None:
         h = np.ascontiguousarray(terrain.h, dtype=np.float32)
