@@ -247,14 +247,21 @@ def main():
                     help="also serve at each of these comma-separated rates [req/s], "
                          "min(--serve-requests, rate * --serve-seconds) arrivals each")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-large", type=int, default=20000,
+                    help="also serve --serve-requests Poisson arrivals at --serve-rate on a table preloaded with "
+                         "this many known plans, with the range query; 0 disables")
     ap.add_argument("--growth", type=int, default=0,
                     help="also serve this many Poisson arrivals at --serve-rate from the known-plan table "
                          "as it grows by every accepted plan (a table sized for all of them); 0 disables")
     ap.add_argument("--sequential", type=int, default=0,
                     help="also plan the first N requests one at a time (plan, then commit) with the full "
                          "sweep and compare with the concurrent pass; 0 disables")
-    ap.add_argument("--lookahead", type=int, default=10,
-                    help="also time one FCFS pass with this scoring window W (full sweep); 0 or 1 disables")
+    ap.add_argument("--range-query", type=int, default=1,
+                    help="also time the full sweep with the range query (only plans within reach of the state "
+                         "swept; same plans); 0 disables")
+    ap.add_argument("--lookahead", default="2,10",
+                    help="also time one FCFS pass with each of these comma-separated scoring windows W "
+                         "(full sweep); empty disables")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work; 0 disables")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -365,26 +372,49 @@ def main():
                                                "pair_evals": prop["pairs"] / len(prop["times"])}
         untrained.close()
 
-    if args.lookahead > 1:
+    if args.range_query:
         import copy
-        lsc = copy.deepcopy(sc)
-        lsc.cfg.lookahead = args.lookahead
-        lctx = fm.context_for(lsc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
+        rsc = copy.deepcopy(sc)
+        rsc.cfg.range_query = 1
+        rctx = fm.context_for(rsc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
                               planner_threads=args.planner_threads)
-        lctx.snapshot()
-        name = f"window {args.lookahead}"
-        r = _leg(lctx, reqs, fm.PROPOSE_NONE, None, args.top_k, 1, 1, name)
-        lst = np.array([p.status for p in r["plans"]])
-        out["lookahead"] = {
-            "window": args.lookahead, "value": r["value"], "ms_per_step": r["ms_per_step"],
-            "planner_steps": r["steps"], "pair_evals_per_s": r["pairs"] / (r["kms"] * 1e-3), "resumes": r["resumes"],
-            "committed_per_step": int(r["committed"].sum()),
-            "status_counts": {S.STATUS_NAMES[int(k)]: int((lst == k).sum()) for k in np.unique(lst)},
-            "roofline": _roofline(r, "lookahead"),
+        rctx.snapshot()
+        r = _leg(rctx, reqs, fm.PROPOSE_NONE, None, args.top_k, args.steps, args.warmup, "range query")
+        same = _same_plans(r["plans"], full["plans"]) and np.array_equal(r["committed"], full["committed"])
+        out["range_query"] = {
+            "value": r["value"], "ms_per_step": r["ms_per_step"], "planner_steps": r["steps"],
+            "identical_to_full_sweep": bool(same), "resumes": r["resumes"],
+            "pairs_swept_per_step": r["pairs"] / len(r["times"]),
+            "pairs_of_full_sweep_per_step": full["pairs"] / len(full["times"]),
+            "roofline": _roofline(r, "range_query"),
         }
-        log(f"{name}: {r['value']:.0f} req/s, committed {int(r['committed'].sum())}/{reqs.n}, "
-            f"status {out['lookahead']['status_counts']}")
-        lctx.close()
+        log(f"range query: {r['value']:.0f} req/s, identical to the full sweep: {same}, pairs swept "
+            f"{out['range_query']['pairs_swept_per_step']:.3e} of {out['range_query']['pairs_of_full_sweep_per_step']:.3e}")
+        rctx.close()
+
+    windows = [int(x) for x in args.lookahead.split(",") if x.strip() and int(x) > 1]
+    if windows:
+        import copy
+        out["lookahead"] = []
+        for W in windows:
+            lsc = copy.deepcopy(sc)
+            lsc.cfg.lookahead = W
+            lctx = fm.context_for(lsc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
+                                  planner_threads=args.planner_threads)
+            lctx.snapshot()
+            name = f"window {W}"
+            r = _leg(lctx, reqs, fm.PROPOSE_NONE, None, args.top_k, 1, 1, name)
+            lst = np.array([p.status for p in r["plans"]])
+            out["lookahead"].append({
+                "window": W, "value": r["value"], "ms_per_step": r["ms_per_step"],
+                "planner_steps": r["steps"], "pair_evals_per_s": r["pairs"] / (r["kms"] * 1e-3),
+                "resumes": r["resumes"], "committed_per_step": int(r["committed"].sum()),
+                "status_counts": {S.STATUS_NAMES[int(k)]: int((lst == k).sum()) for k in np.unique(lst)},
+                "roofline": _roofline(r, "lookahead"),
+            })
+            log(f"{name}: {r['value']:.0f} req/s, committed {int(r['committed'].sum())}/{reqs.n}, "
+                f"status {out['lookahead'][-1]['status_counts']}")
+            lctx.close()
 
     if args.sequential > 0:
         out["sequential_full_sweep"] = _sequential(ctx, reqs, min(args.sequential, reqs.n), full)
@@ -410,6 +440,25 @@ def main():
                 f"p50 {r['p50_latency_ms']:.1f} ms, p99 {r['p99_latency_ms']:.1f} ms, "
                 f"queue mean {r['mean_queue_depth']:.2f} max {r['max_queue_depth']}, "
                 f"resumes/request {r['resumes_per_request']:.3f}")
+    if args.serve_large > 0 and args.serve_rate > 0:
+        t = time.perf_counter()
+        big = S.large_actions(seed=args.seed, n_plans=args.serve_large, n_requests=args.serve_requests)
+        big.cfg.range_query = 1
+        bctx = fm.context_for(big, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
+                              planner_threads=args.planner_threads)
+        bctx.snapshot()
+        log(f"serving on {big.plans.n} known plans (drawn and loaded in {time.perf_counter() - t:.1f} s), "
+            f"{args.serve_requests} arrivals at {args.serve_rate:g} req/s, range query ...")
+        r = _serve(bctx, big, S, args.serve_rate, args.serve_requests)
+        r["known_plans"] = int(big.plans.n)
+        r["method"] = "full sweep with the range query"
+        out["serving_large"] = r
+        log(f"serving on {big.plans.n} plans: achieved {r['achieved_req_s']:.1f} req/s, p50 "
+            f"{r['p50_latency_ms']:.1f} ms, p99 {r['p99_latency_ms']:.1f} ms, queue mean {r['mean_queue_depth']:.2f} "
+            f"max {r['max_queue_depth']}, committed {r['committed']}")
+        bctx.close()
+        del big
+
     if args.growth > 0:
         g = S.large_actions(seed=args.seed, n_plans=args.plans, n_requests=args.growth)
         gctx = fm.context_for(g, max_slots=args.slots, steps_per_launch=args.steps_per_launch,

@@ -107,6 +107,18 @@ typedef struct {
                                         successor inside an intruder well still
                                         rejects.  W > 1 runs the full sweep at
                                         every step (no proposal). */
+    int32_t range_query;             /* 1: without a proposal, each step sweeps
+                                        only the plans within reach of the state
+                                        (max(R_intr, R_sep) + 1 m + the longest
+                                        action step; W > 1 adds (W-1) steps), a
+                                        range query over the row (Sec. VII: range
+                                        queries restrict the trajectories
+                                        considered to the relevant volume).  A
+                                        plan outside that ball cannot reach any
+                                        scored point's well or the commit
+                                        check's reach, so values and plans are
+                                        those of the full sweep; pair counts
+                                        then count the plans swept.  0: off. */
 } fastmdp_config;
 
 /* A plan request: aircraft identifier, source and destination (Sec. I),

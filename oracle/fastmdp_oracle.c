@@ -165,12 +165,15 @@ static int window(const orc_config *c) { return c->lookahead > 1 ? c->lookahead 
  * over the plans active at row t, one peak per plan, evaluated literally.
  * Also the nearest plan distance and whether any distance lies within the
  * boundary band of the radius. */
-static double intruder_term(const orc_world *w, const double p[3], int32_t t, double *dnear, int *amb) {
+static double intruder_term(const orc_world *w, const double p[3], int32_t t, const double *state, double *dnear,
+                            int *amb) {
     const orc_config *c = &w->cfg;
     double Ineg = 0.0, dn = INFINITY;
     for (int j = 0; j < w->n_plans; ++j) {
         double q[3];
         if (!plan_point(&w->plans[j], t, q)) continue;
+        /* range query: only plans within range_radius of the state */
+        if (state && c->range_radius > 0.0 && dist3(state, q) >= c->range_radius) continue;
         double d = dist3(p, q);
         int in = d < c->R_intr;
         double val = in ? fabs(c->r_intr) * pow(c->gamma_intr, d / w->ell) : 0.0;
@@ -237,7 +240,7 @@ int orc_eval_step(const orc_world *w, const double s[3], const double g[3], int3
             /* negative peaks: one risk well per plan active at this point's
              * time, and the terrain clearance well */
             double dnear;
-            double Ineg = intruder_term(w, sp, t + k, &dnear, &ambiguous);
+            double Ineg = intruder_term(w, sp, t + k, s, &dnear, &ambiguous);
             double Tneg = terrain_term(w, sp, &ambiguous);
 
             double value = Gp - (Ineg > Tneg ? Ineg : Tneg);
@@ -316,7 +319,7 @@ int orc_plan(const orc_world *w, const double origin[3], const double goal[3], i
              * chosen successor's own well, whatever the window scored) */
             double dn;
             int amb_unused = 0;
-            if (intruder_term(w, s, t, &dn, &amb_unused) > 0.0) { st = ORC_REJECT_SEPARATION; break; }
+            if (intruder_term(w, s, t, NULL, &dn, &amb_unused) > 0.0) { st = ORC_REJECT_SEPARATION; break; }
             if (w->terr && s[2] - terrain_height(w, s[0], s[1]) < 0.0) { st = ORC_REJECT_TERRAIN; break; }
         }
     }

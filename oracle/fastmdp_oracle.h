@@ -34,6 +34,9 @@
  *     the first point leaves the box (window points outside it are left
  *     out); the state advances by one step; W = 1 scores the successor
  *     alone;
+ *   - range query (Sec. VII): with range_radius > 0 only the plans within
+ *     that distance of the state take part in a step (dmin then reports the
+ *     nearest of those);
  *   - kinematic action model: heading offsets 2*pi*h/H from the goal bearing,
  *     climb rates and speeds from the config; action index a = (h*C + c)*S + v;
  *   - the airspace box is a hard mask (value -inf outside);
@@ -85,6 +88,8 @@ typedef struct {
     double tie_rel;                       /* argmax tie band (relative)    */
     double amb_band;                      /* boundary-ambiguity band [m]   */
     int32_t lookahead;                    /* window W >= 1 (0 reads as 1)  */
+    double range_radius;                  /* > 0: plans farther than this
+                                             from the state are skipped   */
 } orc_config;
 
 typedef struct orc_world orc_world;

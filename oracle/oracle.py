@@ -47,6 +47,7 @@ class _Cfg(C.Structure):
         ("tie_rel", C.c_double),
         ("amb_band", C.c_double),
         ("lookahead", C.c_int32),
+        ("range_radius", C.c_double),
     ]
 
 
@@ -109,6 +110,7 @@ def make_cfg(cfg) -> _Cfg:
     c.tie_rel = float(getattr(cfg, "tie_rel", TIE_REL))
     c.amb_band = float(getattr(cfg, "amb_band", AMB_BAND))
     c.lookahead = int(getattr(cfg, "lookahead", 1))
+    c.range_radius = float(getattr(cfg, "range_radius", 0.0))
     return c
 
 

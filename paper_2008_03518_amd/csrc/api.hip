@@ -176,6 +176,7 @@ int check_cfg(const fastmdp_config *c) {
     if (!(c->tie_rel >= 0.0)) return FASTMDP_E_INVAL;
     if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads) return FASTMDP_E_INVAL;
     if (c->lookahead < 0 || c->lookahead > fmdp::kMaxLookahead) return FASTMDP_E_INVAL;
+    if (c->range_query != 0 && c->range_query != 1) return FASTMDP_E_INVAL;
     return 0;
 }
 
@@ -220,6 +221,11 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.max_steps = c.max_steps;
     d.lookahead = c.lookahead > 1 ? c.lookahead : 1;
     d.max_step = std::sqrt(vmax * vmax + cmax * cmax) * c.dt;
+    d.range_query = c.range_query ? 1 : 0;
+    // every point scored in a step lies within lookahead * max_step of the
+    // state; a plan farther than reach from all of them changes nothing
+    const double rc = d.reach + d.lookahead * d.max_step + 1.0;
+    d.cull_r2 = (float)(rc * rc);
 }
 
 // Adds the last planner launch's duration (its events have completed).

@@ -42,6 +42,8 @@ struct DevCfg {
     int zero_climb;                      // index of the zero climb rate in the middle, else -1
     int max_steps;
     int lookahead;                       // scoring window W >= 1 (Alg. 1 forward projections)
+    int range_query;                     // 1: stage only the row entries within cull_r2 of the state
+    float cull_r2;                       // squared staging radius of the range query (FP32, 1 m margin)
     double max_step;                     // longest action step [m]: window point w lies within
                                          // w * max_step of the state
 };

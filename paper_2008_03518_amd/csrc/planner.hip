@@ -167,7 +167,7 @@ struct PlanGeom {
     static_assert(TILE % (4 * NT) == 0, "a chunk is a whole number of four-entry groups per thread");
 };
 
-template <int NT, int NC, int NV, int ZC, bool PROP, bool LOOK = false>
+template <int NT, int NC, int NV, int ZC, bool PROP, bool LOOK = false, bool CULL = false>
 __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list,
                                                      Traj tr, int budget, int validate, int epoch, EvalOut ev,
                                                      PropArgs prop, LaunchStop stop) {
@@ -354,6 +354,59 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         // the wave's visible entries of lower i and of lower lanes at i
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of the chunk landed
         take_stop();
+        if constexpr (CULL) {
+            // range query: of the visible entries only those within the
+            // staging radius of the state (farther plans cannot reach any
+            // scored point's well), so the offsets come before the ballots
+            float4 e[PRE4][4];
+            bool pv[PRE4][4];
+            uint64_t bal[PRE4][4];
+            int wcnt = 0;
+#pragma unroll
+            for (int i = 0; i < PRE4; ++i) {
+                const int j = 4 * tid + i * 4 * NT;
+                const int4 k4 = *reinterpret_cast<const int4 *>(rawK + j);
+                const float4 x4 = *reinterpret_cast<const float4 *>(rawX + j);
+                const float4 y4 = *reinterpret_cast<const float4 *>(rawY + j);
+                const float4 z4 = *reinterpret_cast<const float4 *>(rawZ + j);
+                const int kv4[4] = {k4.x, k4.y, k4.z, k4.w};
+                const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+                const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
+                const float zs[4] = {z4.x, z4.y, z4.z, z4.w};
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const float qx = (float)((double)xs[m] - s[0]);
+                    const float qy = (float)((double)ys[m] - s[1]);
+                    const float qz = (float)((double)zs[m] - s[2]);
+                    const float w = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+                    e[i][m] = make_float4(qx, qy, cfg.zeta_scale * qz, w);
+                    pv[i][m] = j + m < pre_lim && kv4[m] < seq && w < cfg.cull_r2;
+                    bal[i][m] = __ballot(pv[i][m]);
+                    wcnt += __popcll(bal[i][m]);
+                }
+            }
+            if (lane == 0) s_wsum[wave] = wcnt;
+            lds_barrier();
+            int pos = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int t = s_wsum[w];
+                pos += w < wave ? t : 0;
+                total += t;
+            }
+#pragma unroll
+            for (int i = 0; i < PRE4; ++i)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (pv[i][m]) {
+                        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[i][m] >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal[i][m], 0));
+                        tile[pos + below] = e[i][m];
+                    }
+                    pos += __popcll(bal[i][m]);
+                }
+            return total;
+        }
         // each lane stages the four-entry groups its own loads brought
         bool pv[PRE4][4];
         uint64_t bal[PRE4][4];
@@ -1149,8 +1202,11 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 float m8[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) m8[j] = INFINITY;
+                // (with the range query, slices at or past the staged count
+                // swept nothing)
+                const int n_fold = CULL ? min(n_part, n_vis) : n_part;
                 int q = 0;
-                for (; q + 8 <= n_part; q += 8) {
+                for (; q + 8 <= n_fold; q += 8) {
                     float r8[8];
 #pragma unroll
                     for (int j = 0; j < 8; ++j) r8[j] = red[(q + j) * A + a];
@@ -1161,7 +1217,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
 #pragma unroll
                     for (int j = 0; j < 8; ++j) m8[j] = fminf(m8[j], r8[j]);
                 }
-                for (; q < n_part; ++q) m8[0] = fminf(m8[0], red[q * A + a]);
+                for (; q < n_fold; ++q) m8[0] = fminf(m8[0], red[q * A + a]);
                 const float m = fminf(fminf(fminf(m8[0], m8[1]), fminf(m8[2], m8[3])),
                                       fminf(fminf(m8[4], m8[5]), fminf(m8[6], m8[7])));
                 const double d2 = nearest_d2<NC, NV>(at, a, m);
@@ -1330,9 +1386,15 @@ static hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, co
                            const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
                            const PropArgs &prop, const LaunchStop &stop) {
     (void)nt;
-    if (c.lookahead > 1)
+    if (c.lookahead > 1 && c.range_query)
+        hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false, true, true>), dim3(nblk),
+                           dim3(kPlanThreads), 0, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+    else if (c.lookahead > 1)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false, true>), dim3(nblk), dim3(kPlanThreads), 0,
                            st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+    else if (prop.mode == FASTMDP_PROPOSE_NONE && c.range_query)
+        hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false, false, true>), dim3(nblk),
+                           dim3(kPlanThreads), 0, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
     else if (prop.mode == FASTMDP_PROPOSE_NONE)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
                            t, s, list, tr, budget, validate, epoch, ev, prop, stop);

@@ -48,7 +48,7 @@ class _Config(C.Structure):
         ("max_steps", C.c_int32), ("plan_capacity", C.c_int32), ("max_rows", C.c_int32),
         ("max_slots", C.c_int32), ("steps_per_launch", C.c_int32), ("planner_threads", C.c_int32),
         ("tie_rel", C.c_double),
-        ("lookahead", C.c_int32),
+        ("lookahead", C.c_int32), ("range_query", C.c_int32),
     ]
 
 
@@ -261,6 +261,7 @@ def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_lau
     c.planner_threads = int(planner_threads)
     c.tie_rel = float(tie_rel)
     c.lookahead = int(getattr(cfg, "lookahead", 1))
+    c.range_query = int(getattr(cfg, "range_query", 0))
     return c
 
 

@@ -55,6 +55,7 @@ class Config:
     plan_capacity: int = 4096    # plans per time row
     max_rows: int = 3601         # time rows in the table
     lookahead: int = 1           # steps W of the scoring window (Alg. 1 forward projections)
+    range_query: int = 0         # 1: sweep only the plans within reach of the state (exact)
 
     @property
     def n_climb(self) -> int:

@@ -352,7 +352,16 @@ def test_proposal_plans_identical_other_shapes(fm, preset):
     net.close()
 
 
-def test_training_gain_over_untrained(fm):
+def test_training_gain_against_the_method_without_it(fm):
+    """What training buys, measured against both methods without a trained
+    network at identical plans: the plain full sweep (every action, every
+    step) and the goal-ranked proposal (the same certificate, ranking by the
+    goal-term bound).  The trained network must evaluate far fewer pairs
+    than the full sweep and certify nearly as many steps as the goal
+    ranking, which is the best ranking this certificate admits (if any k-set
+    certifies a step, the k largest goal terms do; pinned by brute force in
+    the proposal oracle tests), so the trained network can match it but not
+    exceed it; the untrained network shows what the training itself adds."""
     from paper_2008_03518_amd import proposal as PR
     A = S.cfg_large_actions().n_actions
     X, y = PR.generate_dataset([100], 60000, n_requests=150, max_slots=256, log=_log)
@@ -371,13 +380,16 @@ def test_training_gain_over_untrained(fm):
         ctx.snapshot()
         ref, com, st, _ = _run(ctx, sc.requests, fm.PROPOSE_NONE)
         got = {}
-        for name, net in (("untrained", untrained), ("trained", trained)):
-            plans, c2, st2, ps = _run(ctx, sc.requests, fm.PROPOSE_MLP, net)
+        for name, mode, net in (("untrained", fm.PROPOSE_MLP, untrained), ("trained", fm.PROPOSE_MLP, trained),
+                                ("goal-ranked", fm.PROPOSE_GOAL, None)):
+            plans, c2, st2, ps = _run(ctx, sc.requests, mode, net)
             _same_plans(plans, ref)
             assert np.array_equal(c2, com)
-            got[name] = ps["certified"] / max(ps["certified"] + ps["fallbacks"], 1)
-            _log(f"[training] {name}: certified {got[name]:.3f} of steps, pairs {st2['pairs']:.3e} "
-                 f"(full sweep {st['pairs']:.3e})")
-        assert got["trained"] > got["untrained"]
+            got[name] = (ps["certified"] / max(ps["certified"] + ps["fallbacks"], 1), st2["pairs"], st2["kernel_ms"])
+            _log(f"[training] {name}: certified {got[name][0]:.3f} of steps, pairs {st2['pairs']:.3e}, planner "
+                 f"{st2['kernel_ms']:.1f} ms (full sweep: pairs {st['pairs']:.3e}, planner {st['kernel_ms']:.1f} ms)")
+        assert got["trained"][0] > got["untrained"][0] + 0.5
+        assert got["trained"][1] < 0.25 * st["pairs"]            # the full sweep evaluates every pair
+        assert got["trained"][0] >= 0.95 * got["goal-ranked"][0]  # at most the goal ranking's rate
     untrained.close()
     trained.close()

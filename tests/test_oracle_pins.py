@@ -553,3 +553,42 @@ def test_lookahead_equals_nearest_plan_window_maximum():
         fin = np.isfinite(best)
         assert np.array_equal(fin, np.isfinite(r["V"]))
         assert np.allclose(r["V"][fin], best[fin], rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Range query (Sec. VII: restrict the trajectories considered to the volume
+# relevant to the flight).  A plan farther than max(R_I, R_sep) + 1 m + W
+# longest steps from the state is farther than the well radius from every
+# point scored in the step (triangle inequality), so skipping it changes no
+# value; a ball any smaller does change values near plans.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("W", [1, 4])
+def test_range_query_changes_no_value(W):
+    sc = S.small(seed=17, n_plans=150, n_requests=1)
+    cfg = sc.cfg
+    cfg.lookahead = W
+    step = math.hypot(max(cfg.speed), max(abs(c) for c in cfg.climb)) * cfg.dt
+    radius = max(cfg.R_intr, cfg.R_sep) + 1.0 + W * step
+    full = Oracle(cfg, sc.plans)
+    cut = S.Config(**{**cfg.__dict__})
+    cut.range_radius = radius
+    ranged = Oracle(cut, sc.plans)
+    small = S.Config(**{**cfg.__dict__})
+    small.range_radius = cfg.R_intr - 10.0
+    too_small = Oracle(small, sc.plans)
+    off = sc.plans.offsets()
+    rng = np.random.default_rng(3)
+    differs = 0
+    for trial in range(40):
+        j = int(rng.integers(sc.plans.n))
+        t = int(rng.integers(0, max(1, int(sc.plans.length[j]) - 6)))
+        s = sc.plans.xyz[off[j] + t].astype(np.float64) + rng.uniform(-220, 220, 3) * [1, 1, 0.3]
+        s[2] = min(max(s[2], 50.0), 950.0)
+        g = np.array([rng.uniform(0, 10000), rng.uniform(0, 10000), rng.uniform(100, 900)])
+        a, b = full.eval_step(s, g, t), ranged.eval_step(s, g, t)
+        for k in ("V", "G", "I", "T"):
+            assert np.array_equal(a[k], b[k]), (trial, k)
+        assert a["best"] == b["best"]
+        c = too_small.eval_step(s, g, t)
+        differs += int(not np.array_equal(a["I"], c["I"]))
+    assert differs > 5
