@@ -5,15 +5,21 @@ Workload: 30 x 30 x 1.5 km airspace, 3000 known straight constant-speed plans,
 steps per request, 1000 FCFS requests (seeded synthetic inputs).  One bench
 step plans and accepts all 1000 requests first-come-first-served with
 concurrent slots, starting from the 3000-plan table (rewound between steps,
-outside the timed region), through the whole path: the learned action
-proposal (trained beforehand, untimed, with the library's own kernels on
-1M tuples from the plain planner on scenarios of seeds 100-109) with its
-exact certificate and full-sweep fallback.  The same pass with the full
-sweep at every step is timed too, and the two must commit identical plans.
-Printed: one JSON line with requests/s, the planner kernel's roofline
-against the FP32 vector peak (for both passes), ablations of the proposal,
-p50/p99 latency of a Poisson-arrival serving pass, and the FP64 CPU oracle
-timed on a bounded sample of the same requests.
+outside the timed region), including the host transfers of requests and
+plans.  Timed legs, all committing identical plans:
+  * the headline: the exact full sweep with the range query (each step
+    sweeps only the plans within reach of the state, Sec. VII), with a
+    memory-side roofline (row bytes streamed);
+  * the plain full sweep (every plan, every action), with its roofline
+    against the FP32 vector peak;
+  * the learned action proposal (trained beforehand, untimed, with the
+    library's own kernels on 1M tuples from the plain planner on scenarios of
+    seeds 100-109) with its exact certificate, alone and with the range
+    query; ablations: goal ranking without a network, an untrained network.
+Also: p50/p99 latency of Poisson-arrival serving passes, serving on a
+20000-plan table, co-simulated batches (the paper's batch-size experiment),
+lookahead windows, and the FP64 CPU oracle timed on a bounded sample.
+Printed: one JSON line.
 """
 from __future__ import annotations
 
@@ -30,7 +36,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+HBM_PEAK_GBPS = 8000.0              # MI355X published HBM3E bandwidth
 FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared distance
+ROW_ENTRY_BYTES = 16                # one table row entry read by a step: x, y, z, visibility
 
 # HBM bytes per planner launch on this workload, from the FETCH_SIZE /
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
@@ -109,12 +117,12 @@ def _leg(ctx, reqs, mode, net, k, steps, warmup, name, refresh=1):
     for w in range(warmup):
         el, *_ = one()
         log(f"{name} warmup {w}: {el * 1e3:.1f} ms")
-    r = dict(times=[], pairs=0, kms=0.0, launches=0, steps=0, resumes=0, cert=0, fallback=0)
+    r = dict(times=[], pairs=0, kms=0.0, launches=0, steps=0, resumes=0, cert=0, fallback=0, entries=0)
     for i in range(steps):
         el, plans, committed, st, ps = one()
         r["times"].append(el)
         for a, b in (("pairs", "pairs"), ("kms", "kernel_ms"), ("launches", "launches"), ("steps", "steps"),
-                     ("resumes", "resumes")):
+                     ("resumes", "resumes"), ("entries", "row_entries")):
             r[a] += st[b]
         r["cert"] += ps["certified"]
         r["fallback"] += ps["fallbacks"]
@@ -141,6 +149,25 @@ def _roofline(r, leg):
         "kernel": "planner_kernel",
         "avg_launch_ms": r["kms"] / max(r["launches"], 1),
         "flops_per_launch": FLOPS_PER_PAIR * r["pairs"] / max(r["launches"], 1),
+    }
+
+
+def _roofline_rows(r, leg):
+    """Memory-side roofline of a leg that sweeps few pairs: the table rows it
+    streams (16 bytes per row entry per step: x, y, z, visibility) per
+    planner-kernel second, against the HBM peak."""
+    achieved = ROW_ENTRY_BYTES * r["entries"] / (r["kms"] * 1e-3) / 1e9
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS,
+        "traffic": _traffic(leg),
+        "traffic_unit": "HBM bytes per launch",
+        "kernel": "planner_kernel",
+        "avg_launch_ms": r["kms"] / max(r["launches"], 1),
+        "bytes_per_launch": ROW_ENTRY_BYTES * r["entries"] / max(r["launches"], 1),
     }
 
 
@@ -256,9 +283,9 @@ def main():
     ap.add_argument("--sequential", type=int, default=0,
                     help="also plan the first N requests one at a time (plan, then commit) with the full "
                          "sweep and compare with the concurrent pass; 0 disables")
-    ap.add_argument("--range-query", type=int, default=1,
-                    help="also time the full sweep with the range query (only plans within reach of the state "
-                         "swept; same plans); 0 disables")
+    ap.add_argument("--batch-sizes", default="1,5,10,20",
+                    help="also plan co-simulated batches of these sizes among 100 known plans in the 10 km box "
+                         "(the paper's batch-size experiment); empty disables")
     ap.add_argument("--lookahead", default="2,10",
                     help="also time one FCFS pass with each of these comma-separated scoring windows W "
                          "(full sweep); empty disables")
@@ -314,21 +341,32 @@ def main():
     ctx.snapshot()
     full = _leg(ctx, reqs, fm.PROPOSE_NONE, None, args.top_k, args.steps, args.warmup, "full sweep")
     prop = _leg(ctx, reqs, fm.PROPOSE_MLP, net, args.top_k, args.steps, args.warmup, "proposal", args.refresh)
-    identical = _same_plans(prop["plans"], full["plans"]) and np.array_equal(prop["committed"], full["committed"])
-    log(f"proposal plans identical to the full sweep: {identical}")
-    status = np.array([p.status for p in prop["plans"]])
+    prop_same = _same_plans(prop["plans"], full["plans"]) and np.array_equal(prop["committed"], full["committed"])
+    log(f"proposal plans identical to the full sweep: {prop_same}")
+
+    # the headline path: the full sweep with the range query (the same plans)
+    import copy
+    rsc = copy.deepcopy(sc)
+    rsc.cfg.range_query = 1
+    rctx = fm.context_for(rsc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
+                          planner_threads=args.planner_threads)
+    rctx.snapshot()
+    rq = _leg(rctx, reqs, fm.PROPOSE_NONE, None, args.top_k, args.steps, args.warmup, "range query")
+    identical = _same_plans(rq["plans"], full["plans"]) and np.array_equal(rq["committed"], full["committed"])
+    log(f"range query: {rq['value']:.0f} req/s, plans identical to the full sweep: {identical}")
+    status = np.array([p.status for p in rq["plans"]])
 
     def cert_rate(r):
         return r["cert"] / max(r["cert"] + r["fallback"], 1)
 
     out = {
         "metric": "FCFS plan requests/sec at 3000 known plans",
-        "value": prop["value"],
+        "value": rq["value"],
         "unit": "req/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": prop["ms_per_step"],
+        "ms_per_step": rq["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -336,27 +374,41 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{sc.plans.n} known plans, {A} actions (24 headings x 5 climbs x 3 speeds), "
-                        f"dt 0.5 s, {reqs.n} FCFS requests, 30x30x1.5 km; learned proposal top-{args.top_k} "
-                        f"with exact certificate",
+                        f"dt 0.5 s, {reqs.n} FCFS requests, 30x30x1.5 km; exact full sweep with the range query "
+                        f"(only plans within reach of the state are swept; plans identical to the full sweep)",
             "known_plans": sc.plans.n, "actions": A, "requests_per_step": reqs.n,
             "slots": args.slots, "steps_per_launch": args.steps_per_launch,
-            "planner_threads": args.planner_threads, "top_k": args.top_k, "refresh": args.refresh,
+            "planner_threads": args.planner_threads,
         },
         "identical_to_full_sweep": bool(identical),
-        "pair_evals_per_s": prop["pairs"] / (prop["kms"] * 1e-3),
-        "planner_steps": prop["steps"],
-        "certified_step_rate": cert_rate(prop),
-        "resumes": prop["resumes"],
-        "committed_per_step": int(prop["committed"].sum()),
+        "planner_steps": rq["steps"],
+        "resumes": rq["resumes"],
+        "committed_per_step": int(rq["committed"].sum()),
         "status_counts": {S.STATUS_NAMES[int(k)]: int((status == k).sum()) for k in np.unique(status)},
-        "roofline": _roofline(prop, "proposal"),
+        "pairs_swept_per_step": rq["pairs"] / len(rq["times"]),
+        "pairs_of_full_sweep_per_step": full["pairs"] / len(full["times"]),
+        "roofline": _roofline_rows(rq, "range_query"),
         "full_sweep": {
             "value": full["value"], "ms_per_step": full["ms_per_step"], "planner_steps": full["steps"],
             "pair_evals_per_s": full["pairs"] / (full["kms"] * 1e-3), "resumes": full["resumes"],
             "roofline": _roofline(full, "full_sweep"),
         },
+        "proposal": {
+            "value": prop["value"], "ms_per_step": prop["ms_per_step"], "identical_to_full_sweep": bool(prop_same),
+            "top_k": args.top_k, "refresh": args.refresh, "certified_step_rate": cert_rate(prop),
+            "pair_evals_per_s": prop["pairs"] / (prop["kms"] * 1e-3), "resumes": prop["resumes"],
+            "roofline": _roofline(prop, "proposal"),
+        },
         "training": train_info,
     }
+    # the trained proposal with the range query
+    rp = _leg(rctx, reqs, fm.PROPOSE_MLP, net, args.top_k, args.steps, args.warmup, "proposal + range query",
+              args.refresh)
+    same = _same_plans(rp["plans"], full["plans"]) and np.array_equal(rp["committed"], full["committed"])
+    out["proposal_with_range_query"] = {
+        "value": rp["value"], "ms_per_step": rp["ms_per_step"], "identical_to_full_sweep": bool(same),
+        "certified_step_rate": cert_rate(rp), "pairs_swept_per_step": rp["pairs"] / len(rp["times"])}
+    log(f"proposal + range query: {rp['value']:.0f} req/s, identical to the full sweep: {same}")
 
     if args.ablations:
         goal = _leg(ctx, reqs, fm.PROPOSE_GOAL, None, args.top_k, args.steps, 0, "goal-ranked", args.refresh)
@@ -372,25 +424,28 @@ def main():
                                                "pair_evals": prop["pairs"] / len(prop["times"])}
         untrained.close()
 
-    if args.range_query:
-        import copy
-        rsc = copy.deepcopy(sc)
-        rsc.cfg.range_query = 1
-        rctx = fm.context_for(rsc, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
-                              planner_threads=args.planner_threads)
-        rctx.snapshot()
-        r = _leg(rctx, reqs, fm.PROPOSE_NONE, None, args.top_k, args.steps, args.warmup, "range query")
-        same = _same_plans(r["plans"], full["plans"]) and np.array_equal(r["committed"], full["committed"])
-        out["range_query"] = {
-            "value": r["value"], "ms_per_step": r["ms_per_step"], "planner_steps": r["steps"],
-            "identical_to_full_sweep": bool(same), "resumes": r["resumes"],
-            "pairs_swept_per_step": r["pairs"] / len(r["times"]),
-            "pairs_of_full_sweep_per_step": full["pairs"] / len(full["times"]),
-            "roofline": _roofline(r, "range_query"),
-        }
-        log(f"range query: {r['value']:.0f} req/s, identical to the full sweep: {same}, pairs swept "
-            f"{out['range_query']['pairs_swept_per_step']:.3e} of {out['range_query']['pairs_of_full_sweep_per_step']:.3e}")
-        rctx.close()
+    sizes = [int(x) for x in args.batch_sizes.split(",") if x.strip()]
+    if sizes:
+        out["batch"] = []
+        bsc = S.small(seed=7, n_plans=100, n_requests=max(sizes))
+        with fm.context_for(bsc, max_slots=max(sizes)) as bctx:
+            for nb in sizes:
+                breq = S.Requests(bsc.requests.ident[:nb], bsc.requests.origin[:nb], bsc.requests.goal[:nb],
+                                  bsc.requests.t0[:nb])
+                bctx.plan_batch(breq)                               # warm-up
+                t = time.perf_counter()
+                bplans = bctx.plan_batch(breq)
+                el = time.perf_counter() - t
+                bst = bctx.stats()
+                steps = max(p.n_points - 1 for p in bplans)
+                bst_status = np.array([p.status for p in bplans])
+                out["batch"].append({
+                    "batch": nb, "lockstep_steps": steps, "steps_per_s": steps / el,
+                    "aircraft_steps_per_s": bst["steps"] / el, "ms": el * 1e3, "gpu_ms": bst["kernel_ms"],
+                    "status_counts": {S.STATUS_NAMES[int(k)]: int((bst_status == k).sum())
+                                      for k in np.unique(bst_status)}})
+                log(f"batch {nb}: {steps} lockstep steps in {el * 1e3:.1f} ms ({steps / el:.0f} steps/s, "
+                    f"{bst['steps'] / el:.0f} aircraft-steps/s)")
 
     windows = [int(x) for x in args.lookahead.split(",") if x.strip() and int(x) > 1]
     if windows:
@@ -423,18 +478,24 @@ def main():
             f"identical to the concurrent pass: {q['identical_to_concurrent_pass']}")
 
     if args.serve_rate > 0 or args.serve_rates:
+        rctx.set_proposal(fm.PROPOSE_NONE, 1, None, 1)
         ctx.set_proposal(fm.PROPOSE_MLP, args.top_k, net, args.refresh)
     if args.serve_rate > 0:
-        out["serving"] = _serve(ctx, sc, S, args.serve_rate, args.serve_requests)
+        out["serving"] = _serve(rctx, rsc, S, args.serve_rate, args.serve_requests)
+        out["serving"]["method"] = "full sweep with the range query"
         out["p50_latency_ms"] = out["serving"]["p50_latency_ms"]
         out["p99_latency_ms"] = out["serving"]["p99_latency_ms"]
         log(f"serving at {args.serve_rate} req/s: p50 {out['p50_latency_ms']:.1f} ms, "
             f"p99 {out['p99_latency_ms']:.1f} ms")
+        out["serving_proposal"] = _serve(ctx, sc, S, args.serve_rate, args.serve_requests)
+        out["serving_proposal"]["method"] = "trained proposal"
+        log(f"serving with the trained proposal: p50 {out['serving_proposal']['p50_latency_ms']:.1f} ms, "
+            f"p99 {out['serving_proposal']['p99_latency_ms']:.1f} ms")
     if args.serve_rates:
         out["serving_sweep"] = []
         for rate in (float(x) for x in args.serve_rates.split(",")):
             m = max(1, min(args.serve_requests, int(rate * args.serve_seconds)))
-            r = _serve(ctx, sc, S, rate, m)
+            r = _serve(rctx, rsc, S, rate, m)
             out["serving_sweep"].append(r)
             log(f"serving at {rate:g} req/s ({m} requests): achieved {r['achieved_req_s']:.1f} req/s, "
                 f"p50 {r['p50_latency_ms']:.1f} ms, p99 {r['p99_latency_ms']:.1f} ms, "
@@ -461,10 +522,10 @@ def main():
 
     if args.growth > 0:
         g = S.large_actions(seed=args.seed, n_plans=args.plans, n_requests=args.growth)
+        g.cfg.range_query = 1
         gctx = fm.context_for(g, max_slots=args.slots, steps_per_launch=args.steps_per_launch,
                               planner_threads=args.planner_threads)
         gctx.snapshot()
-        gctx.set_proposal(fm.PROPOSE_MLP, args.top_k, net, args.refresh)
         rate = args.serve_rate if args.serve_rate > 0 else 200.0
         log(f"growth: {args.growth} arrivals at {rate:g} req/s from {g.plans.n} plans ...")
         r = _serve(gctx, g, S, rate, args.growth)
@@ -476,6 +537,7 @@ def main():
             f"{r['mean_queue_depth']:.2f} max {r['max_queue_depth']}, resumes/request {r['resumes_per_request']:.3f}")
         gctx.close()
     ctx.close()
+    rctx.close()
     net.close()
 
     if args.cpu_budget > 0:

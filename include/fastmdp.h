@@ -119,6 +119,10 @@ typedef struct {
                                         check's reach, so values and plans are
                                         those of the full sweep; pair counts
                                         then count the plans swept.  0: off. */
+    double peak_growth;              /* co-simulated batches (fastmdp_plan_batch):
+                                        the radius of the peak at time offset tau
+                                        along another aircraft's track is R_intr +
+                                        peak_growth * tau [m/s], >= 0 */
 } fastmdp_config;
 
 /* A plan request: aircraft identifier, source and destination (Sec. I),
@@ -222,6 +226,27 @@ int fastmdp_plan_request(fastmdp_ctx *ctx, const fastmdp_request *req, fastmdp_p
 int fastmdp_plan_departures(fastmdp_ctx *ctx, const fastmdp_request *req, int32_t n, const int32_t *t0,
                             fastmdp_plan *plans, int32_t *chosen);
 
+/* Co-simulated batch (Sec. V: several aircraft planned together, each aware
+ * of the others and of every accepted plan).  The n requests (all with the
+ * same departure row) fly in lockstep.  At each step every aircraft still
+ * flying scores its actions against the known plans, the terrain and five
+ * risk wells per other flying aircraft, placed along that aircraft's
+ * extrapolated track at p + v*tau for tau in {-5, 0, 5, 10, 15} s with
+ * radius R_intr + peak_growth*tau, magnitude r_intr and discount gamma_intr
+ * (the peak table; "Build peaks"; "Process negative rewards"), p its
+ * position and v its last step over dt (0 before its first step); the value
+ * is the goal term less the largest of the intruder, batch and terrain
+ * wells ("Compute value").  Then all apply their choices; an aircraft is
+ * rejected (REJECT_SEPARATION) when a known plan's well contains its new
+ * point or another aircraft that moved in the same step is closer than
+ * R_sep, and an aircraft within one step of its goal or at max_steps is
+ * done at the start of the next step.  One planner launch per step, one
+ * workgroup per aircraft.  plans[i] receives aircraft i (buffers as for
+ * fastmdp_plan_request); nothing is committed.  1 <= n <= 32 and n <=
+ * max_slots; needs lookahead 1 and no proposal.
+ * Errors: E_INVAL, E_CAPACITY, E_DEVICE. */
+int fastmdp_plan_batch(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, fastmdp_plan *plans);
+
 /* Accept a plan into the table (Sec. V: the accepted-plan database grows by
  * one trajectory).  The points are rounded to FP32 and re-validated against
  * every plan in the table (3-D distance >= R_sep at every shared row) and
@@ -266,13 +291,15 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
 int fastmdp_table_snapshot(fastmdp_ctx *ctx);
 int fastmdp_table_rewind(fastmdp_ctx *ctx);
 
-/* Counters of the last fastmdp_plan_request / fastmdp_plan_fcfs /
- * fastmdp_eval_step call: pair evaluations (action x active plan per step),
- * steps taken, resumes, planner launches, and summed planner-kernel time
- * in milliseconds measured with HIP events on the context's stream.  Any
- * pointer may be NULL. */
+/* Counters of the last planning call (fastmdp_plan_request, _plan_fcfs,
+ * _plan_departures, _plan_batch, _eval_step): pair evaluations (action x
+ * plan swept per step), steps taken, resumes, planner launches, summed
+ * planner-kernel time in milliseconds measured with HIP events on the
+ * context's stream, and table row entries read (each step reads the
+ * successor's row, 16 bytes per entry: x, y, z, visibility; every window
+ * row with a window).  Any pointer may be NULL. */
 int fastmdp_last_stats(const fastmdp_ctx *ctx, int64_t *pairs, int64_t *steps, int64_t *resumes,
-                       int64_t *launches, double *kernel_ms);
+                       int64_t *launches, double *kernel_ms, int64_t *row_entries);
 
 /* Checkpoint (the accepted-plan file of Sec. V): write / read the whole
  * table (row counts and FP32 points) to / from a binary file.  Loading

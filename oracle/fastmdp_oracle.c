@@ -214,9 +214,39 @@ static int select_action(const double *V, int A, double tie_rel) {
     return -1;
 }
 
+/* Risk wells of the peaks built from other aircraft of a co-simulated batch
+ * (peaks[4k..4k+3] = x, y, z, radius): the largest [d < R_k] |r| gamma^(d/ell),
+ * one peak at a time. */
+static double mate_term(const orc_world *w, const double p[3], const double *peaks, int np, int *amb) {
+    const orc_config *c = &w->cfg;
+    double M = 0.0;
+    for (int k = 0; k < np; ++k) {
+        const double *q = peaks + 4 * k;
+        double d = dist3(p, q);
+        int in = d < q[3];
+        double val = in ? fabs(c->r_intr) * pow(c->gamma_intr, d / w->ell) : 0.0;
+        if (val > M) M = val;
+        if (fabs(d - q[3]) <= c->amb_band) *amb = 1;
+    }
+    return M;
+}
+
+static int eval_core(const orc_world *w, const double s[3], const double g[3], int32_t t, const double *peaks,
+                     int np, double *V, double *G, double *I, double *T, double *dmin, int32_t *amb, int32_t *best);
+
 int orc_eval_step(const orc_world *w, const double s[3], const double g[3], int32_t t,
                   double *V, double *G, double *I, double *T, double *dmin,
                   int32_t *amb, int32_t *best) {
+    return eval_core(w, s, g, t, NULL, 0, V, G, I, T, dmin, amb, best);
+}
+
+/* Score every action; with np > 0 the peaks of the other aircraft of a
+ * co-simulated batch add their wells ("Process negative rewards"), and the
+ * value is the goal term less the largest of the three penalty classes
+ * ("Compute value"); I then reports the larger of the intruder and batch
+ * wells. */
+static int eval_core(const orc_world *w, const double s[3], const double g[3], int32_t t, const double *peaks,
+                     int np, double *V, double *G, double *I, double *T, double *dmin, int32_t *amb, int32_t *best) {
     if (!w || !s || !g || t < 0) return ORC_E_INVAL;
     const orc_config *c = &w->cfg;
     const int A = c->n_head * c->n_climb * c->n_speed;
@@ -241,6 +271,10 @@ int orc_eval_step(const orc_world *w, const double s[3], const double g[3], int3
              * time, and the terrain clearance well */
             double dnear;
             double Ineg = intruder_term(w, sp, t + k, s, &dnear, &ambiguous);
+            if (np > 0) {
+                double Mneg = mate_term(w, sp, peaks, np, &ambiguous);
+                if (Mneg > Ineg) Ineg = Mneg;
+            }
             double Tneg = terrain_term(w, sp, &ambiguous);
 
             double value = Gp - (Ineg > Tneg ? Ineg : Tneg);
@@ -326,6 +360,112 @@ int orc_plan(const orc_world *w, const double origin[3], const double goal[3], i
     *n_pts = n;
     *status = st;
     free(V); free(I); free(T);
+    return 0;
+}
+
+/* Time offsets [s] of the five peaks placed along another aircraft's
+ * extrapolated track (Table "Peaks created in the environment"). */
+static const double mate_tau[ORC_MATE_PEAKS] = {-5.0, 0.0, 5.0, 10.0, 15.0};
+
+int orc_plan_batch(const orc_world *w, int32_t n, const double *origins, const double *goals, int32_t t0,
+                   int32_t cap, double *xyz, int32_t *act, double *val, int32_t *n_pts, int32_t *status) {
+    if (!w || n < 1 || !origins || !goals || t0 < 0 || cap < 1 || !xyz || !act || !val || !n_pts || !status)
+        return ORC_E_INVAL;
+    const orc_config *c = &w->cfg;
+    const int A = c->n_head * c->n_climb * c->n_speed;
+    double *V = (double *)malloc((size_t)A * sizeof(double));
+    double *peaks = (double *)malloc((size_t)n * ORC_MATE_PEAKS * 4 * sizeof(double));
+    int32_t *choice = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    double *vals = (double *)malloc((size_t)n * sizeof(double));
+    int *moved = (int *)malloc((size_t)n * sizeof(int));
+    if (!V || !peaks || !choice || !vals || !moved) {
+        free(V); free(peaks); free(choice); free(vals); free(moved);
+        return ORC_E_NOMEM;
+    }
+    /* aircraft i's point k is xyz[(i * cap + k) * 3] */
+    for (int i = 0; i < n; ++i) {
+        double *x = xyz + (size_t)i * cap * 3;
+        x[0] = origins[3 * i]; x[1] = origins[3 * i + 1]; x[2] = origins[3 * i + 2];
+        act[(size_t)i * cap] = -1;
+        val[(size_t)i * cap] = 0.0;
+        n_pts[i] = 1;
+        status[i] = origin_blocked(w, x, t0) ? ORC_REJECT_ORIGIN : -1;   /* -1: flying */
+    }
+    for (int32_t k = 0;; ++k) {
+        const int32_t t = t0 + k;
+        /* 1. goal capture and step limit of every aircraft still flying */
+        int flying = 0;
+        for (int i = 0; i < n; ++i) {
+            if (status[i] != -1) continue;
+            const double *s = xyz + ((size_t)i * cap + n_pts[i] - 1) * 3;
+            if (dist3(goals + 3 * i, s) <= w->ell) status[i] = ORC_OK;
+            else if (k == c->max_steps || n_pts[i] == cap) status[i] = ORC_TIMEOUT;
+            else flying += 1;
+        }
+        if (!flying) break;
+        /* 2.-3. every flying aircraft scores its actions against the known
+         * plans, the terrain and the five peaks of every other flying
+         * aircraft, built from its position and velocity now (the set of
+         * flying aircraft is the one at the start of the step: choices are
+         * made before any of them is applied) */
+        for (int i = 0; i < n; ++i) moved[i] = status[i] == -1;   /* flying in this step */
+        for (int i = 0; i < n; ++i) {
+            choice[i] = -1;
+            if (!moved[i]) continue;
+            int np = 0;
+            for (int j = 0; j < n; ++j) {
+                if (j == i || !moved[j]) continue;
+                const double *pj = xyz + ((size_t)j * cap + n_pts[j] - 1) * 3;
+                double vj[3] = {0.0, 0.0, 0.0};
+                if (n_pts[j] > 1) {
+                    const double *qj = pj - 3;
+                    for (int a = 0; a < 3; ++a) vj[a] = (pj[a] - qj[a]) / c->dt;
+                }
+                for (int m = 0; m < ORC_MATE_PEAKS; ++m, ++np) {
+                    double *pk = peaks + 4 * np;
+                    for (int a = 0; a < 3; ++a) pk[a] = pj[a] + vj[a] * mate_tau[m];
+                    pk[3] = c->R_intr + c->peak_growth * mate_tau[m];
+                }
+            }
+            const double *s = xyz + ((size_t)i * cap + n_pts[i] - 1) * 3;
+            int best = -1;
+            eval_core(w, s, goals + 3 * i, t, peaks, np, V, NULL, NULL, NULL, NULL, NULL, &best);
+            choice[i] = best;
+            vals[i] = best >= 0 ? V[best] : 0.0;
+        }
+        /* 4. all apply their choices */
+        for (int i = 0; i < n; ++i) {
+            if (!moved[i]) continue;
+            if (choice[i] < 0) {
+                status[i] = ORC_NO_VALID_ACTION;
+                moved[i] = 0;
+                continue;
+            }
+            const double *s = xyz + ((size_t)i * cap + n_pts[i] - 1) * 3;
+            double sp[3];
+            successor(c, s, goal_bearing(s, goals + 3 * i), choice[i], sp);
+            double *x = xyz + ((size_t)i * cap + n_pts[i]) * 3;
+            x[0] = sp[0]; x[1] = sp[1]; x[2] = sp[2];
+            act[(size_t)i * cap + n_pts[i]] = choice[i];
+            val[(size_t)i * cap + n_pts[i]] = vals[i];
+            n_pts[i] += 1;
+        }
+        /* 5. collisions at the new positions: a known plan within its well
+         * (R_intr = R_sep), another aircraft of the batch that moved in this
+         * step closer than R_sep, the terrain */
+        for (int i = 0; i < n; ++i) {
+            if (!moved[i]) continue;
+            const double *x = xyz + ((size_t)i * cap + n_pts[i] - 1) * 3;
+            double dn;
+            int amb_unused = 0;
+            int hit = intruder_term(w, x, t + 1, NULL, &dn, &amb_unused) > 0.0;
+            for (int j = 0; j < n && !hit; ++j)
+                if (j != i && moved[j] && dist3(x, xyz + ((size_t)j * cap + n_pts[j] - 1) * 3) < c->R_sep) hit = 1;
+            if (hit) status[i] = ORC_REJECT_SEPARATION;
+            else if (w->terr && x[2] - terrain_height(w, x[0], x[1]) < 0.0) status[i] = ORC_REJECT_TERRAIN;
+        }
+    }
+    free(V); free(peaks); free(choice); free(vals); free(moved);
     return 0;
 }
 

@@ -90,7 +90,11 @@ typedef struct {
     int32_t lookahead;                    /* window W >= 1 (0 reads as 1)  */
     double range_radius;                  /* > 0: plans farther than this
                                              from the state are skipped   */
+    double peak_growth;                   /* batch peaks: radius R_intr +
+                                             peak_growth * tau [m/s]      */
 } orc_config;
+
+#define ORC_MATE_PEAKS 5
 
 typedef struct orc_world orc_world;
 
@@ -125,6 +129,26 @@ int  orc_eval_step(const orc_world *w, const double s[3], const double g[3], int
 int  orc_plan(const orc_world *w, const double origin[3], const double goal[3], int32_t t0,
               int32_t cap, double *xyz, int32_t *act, double *val,
               int32_t *n_pts, int32_t *status);
+
+/* Co-simulated batch (Sec. V: several aircraft planned together, aware of
+ * each other and of every accepted plan): n aircraft departing at row t0,
+ * in lockstep.  Each step: (1) an aircraft within ell of its goal is done
+ * (OK), one that has taken max_steps times out; (2) every aircraft still
+ * flying scores its actions against the known plans, the terrain and five
+ * risk wells per other flying aircraft, placed along that aircraft's
+ * extrapolated track at p + v*tau, tau in {-5, 0, 5, 10, 15} s, radius
+ * R_intr + peak_growth*tau, magnitude |r_intr|, discount gamma_intr (Table
+ * "Peaks created in the environment"; "Build peaks"; "Process negative
+ * rewards"), with p its position and v its last step over dt (0 before its
+ * first step), and chooses as for one aircraft; (3) all apply their choices
+ * ("Now that all aircraft have selected an action, apply it"); (4) an
+ * aircraft is rejected (REJECT_SEPARATION) if a known plan lies inside its
+ * well at the new row or another aircraft that moved in this step is
+ * closer than R_sep, and (REJECT_TERRAIN) if below the terrain.  Aircraft
+ * i's points go to xyz[(i*cap + k)*3 ..], act[i*cap + k], val[i*cap + k];
+ * n_pts[i], status[i] as for orc_plan.  Nothing is committed. */
+int  orc_plan_batch(const orc_world *w, int32_t n, const double *origins, const double *goals, int32_t t0,
+                    int32_t cap, double *xyz, int32_t *act, double *val, int32_t *n_pts, int32_t *status);
 
 /* Validate a trajectory as planned (FP64) against every plan in the table
  * as stored (FP32) and against the terrain; if clear, append it rounded to

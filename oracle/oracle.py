@@ -48,6 +48,7 @@ class _Cfg(C.Structure):
         ("amb_band", C.c_double),
         ("lookahead", C.c_int32),
         ("range_radius", C.c_double),
+        ("peak_growth", C.c_double),
     ]
 
 
@@ -73,6 +74,7 @@ def _load():
         lib.orc_eval_step.argtypes = [P, dp, dp, C.c_int32, dp, dp, dp, dp, dp, ip, ip]
         lib.orc_plan.argtypes = [P, dp, dp, C.c_int32, C.c_int32, dp, ip, dp, ip, ip]
         lib.orc_commit.argtypes = [P, C.c_int32, C.c_int32, dp]
+        lib.orc_plan_batch.argtypes = [P, C.c_int32, dp, dp, C.c_int32, C.c_int32, dp, ip, dp, ip, ip]
         lib.orc_num_threads.argtypes = []
         _lib = lib
     return _lib
@@ -111,6 +113,7 @@ def make_cfg(cfg) -> _Cfg:
     c.amb_band = float(getattr(cfg, "amb_band", AMB_BAND))
     c.lookahead = int(getattr(cfg, "lookahead", 1))
     c.range_radius = float(getattr(cfg, "range_radius", 0.0))
+    c.peak_growth = float(getattr(cfg, "peak_growth", 10.0))
     return c
 
 
@@ -209,6 +212,24 @@ class Oracle:
             raise ValueError(f"orc_plan failed: {rc}")
         k = int(n[0])
         return OraclePlan(int(st[0]), t0, xyz[:k].copy(), act[:k].copy(), val[:k].copy())
+
+    def plan_batch(self, origins, goals, t0: int = 0, cap: Optional[int] = None):
+        """Plan n aircraft co-simulated in lockstep (see orc_plan_batch)."""
+        cap = int(cap or (self.cfg.max_steps + 1))
+        origins = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
+        goals = np.ascontiguousarray(goals, dtype=np.float64).reshape(-1, 3)
+        n = origins.shape[0]
+        xyz = np.zeros((n, cap, 3))
+        act = np.zeros((n, cap), dtype=np.int32)
+        val = np.zeros((n, cap))
+        npts = np.zeros(n, dtype=np.int32)
+        st = np.zeros(n, dtype=np.int32)
+        rc = self.lib.orc_plan_batch(self._h, n, _dptr(origins), _dptr(goals), int(t0), cap, _dptr(xyz), _iptr(act),
+                                     _dptr(val), _iptr(npts), _iptr(st))
+        if rc != 0:
+            raise ValueError(f"orc_plan_batch failed: {rc}")
+        return [OraclePlan(int(st[i]), t0, xyz[i, :npts[i]].copy(), act[i, :npts[i]].copy(), val[i, :npts[i]].copy())
+                for i in range(n)]
 
     def commit(self, plan_or_t0, xyz=None) -> bool:
         """Validate and append; False (table unchanged) on a separation conflict."""

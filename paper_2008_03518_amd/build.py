@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["api.hip", "planner.hip", "table.hip", "features.hip", "mlp.hip", "devmem.hip"]
+SOURCES = ["api.hip", "planner.hip", "table.hip", "batch.hip", "features.hip", "mlp.hip", "devmem.hip"]
 LIB = os.path.join(PKG, "libfastmdp.so")
 
 HIPCC_FLAGS = [

@@ -109,9 +109,10 @@ struct fastmdp_ctx {
     int *dEvI = nullptr;          // top-k, certified, proposal's action
     int *dStop = nullptr;         // finished-workgroup counter of a planner launch
     int *dPass = nullptr;         // slots of an acceptance pass
+    fmdp::BatchState bs{};        // co-simulated batch: peaks and step bookkeeping
     std::mutex mu;
     // counters of the last call
-    long long st_pairs = 0, st_steps = 0, st_resumes = 0, st_launches = 0;
+    long long st_pairs = 0, st_steps = 0, st_resumes = 0, st_launches = 0, st_entries = 0;
     long long st_hit = 0, st_miss = 0;
     double st_ms = 0.0;
 };
@@ -151,6 +152,8 @@ void free_all(fastmdp_ctx *c) {
     if (c->hGather) hipHostFree(c->hGather);
     hipFree(c->dGather); hipFree(c->dList2); hipFree(c->dOff);
     hipFree(c->dEvF); hipFree(c->dEvI); hipFree(c->dStop); hipFree(c->dPass);
+    hipFree(c->bs.pk); hipFree(c->bs.owner); hipFree(c->bs.n); hipFree(c->bs.active); hipFree(c->bs.prev_n);
+    hipFree(c->bs.any);
     if (c->e0) hipEventDestroy(c->e0);
     if (c->e1) hipEventDestroy(c->e1);
     if (c->eGather) hipEventDestroy(c->eGather);
@@ -177,6 +180,7 @@ int check_cfg(const fastmdp_config *c) {
     if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads) return FASTMDP_E_INVAL;
     if (c->lookahead < 0 || c->lookahead > fmdp::kMaxLookahead) return FASTMDP_E_INVAL;
     if (c->range_query != 0 && c->range_query != 1) return FASTMDP_E_INVAL;
+    if (!(c->peak_growth >= 0.0)) return FASTMDP_E_INVAL;
     return 0;
 }
 
@@ -222,6 +226,7 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     d.lookahead = c.lookahead > 1 ? c.lookahead : 1;
     d.max_step = std::sqrt(vmax * vmax + cmax * cmax) * c.dt;
     d.range_query = c.range_query ? 1 : 0;
+    d.peak_growth = c.peak_growth;
     // every point scored in a step lies within lookahead * max_step of the
     // state; a plan farther than reach from all of them changes nothing
     const double rc = d.reach + d.lookahead * d.max_step + 1.0;
@@ -238,13 +243,14 @@ int planner_time(fastmdp_ctx *c) {
 }
 
 int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int validate, int epoch,
-                  const EvalOut &ev, int stop_target = 0, bool sync = true) {
+                  const EvalOut &ev, int stop_target = 0, bool sync = true,
+                  const fmdp::MatePeaks &mates = fmdp::MatePeaks{}) {
     const int nt = fmdp::kPlanThreads;
     HIP_TRY(hipEventRecord(c->e0, c->stream));
     const fmdp::LaunchStop stop{c->dStop, stop_target};
     if (stop_target > 0) HIP_TRY(fmdp::launch_fill_int(c->dStop, 0, 1, c->stream));
     hipError_t e = fmdp::launch_planner(nblk, nt, c->stream, c->dc, c->tb, c->dSlots, list, c->tr, budget, validate,
-                                        epoch, ev, c->prop, stop);
+                                        epoch, ev, c->prop, stop, mates);
     if (e != hipSuccess) {
         std::fprintf(stderr, "libfastmdp: planner launch failed: %s\n", hipGetErrorString(e));
         return FASTMDP_E_DEVICE;
@@ -256,7 +262,7 @@ int timed_planner(fastmdp_ctx *c, int nblk, const int *list, int budget, int val
 }
 
 void reset_stats(fastmdp_ctx *c) {
-    c->st_pairs = c->st_steps = c->st_resumes = c->st_launches = 0;
+    c->st_pairs = c->st_steps = c->st_resumes = c->st_launches = c->st_entries = 0;
     c->st_hit = c->st_miss = 0;
     c->st_ms = 0.0;
 }
@@ -419,6 +425,12 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->dEvI, (size_t)FASTMDP_MAX_TOPK + 2);
     rc = rc ? rc : dev_alloc(&c->dStop, (size_t)1);
     rc = rc ? rc : dev_alloc(&c->dPass, (size_t)c->max_slots);
+    rc = rc ? rc : dev_alloc(&c->bs.pk, (size_t)fmdp::kMaxBatch * fmdp::kMatePeaks * 4);
+    rc = rc ? rc : dev_alloc(&c->bs.owner, (size_t)fmdp::kMaxBatch * fmdp::kMatePeaks);
+    rc = rc ? rc : dev_alloc(&c->bs.n, (size_t)1);
+    rc = rc ? rc : dev_alloc(&c->bs.active, (size_t)fmdp::kMaxBatch);
+    rc = rc ? rc : dev_alloc(&c->bs.prev_n, (size_t)fmdp::kMaxBatch);
+    rc = rc ? rc : dev_alloc(&c->bs.any, (size_t)1);
     if (!rc && hipHostMalloc(reinterpret_cast<void **>(&c->hSlots), (size_t)c->max_slots * sizeof(Slot)) != hipSuccess)
         rc = FASTMDP_E_NOMEM;
     if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
@@ -613,6 +625,7 @@ int fastmdp_eval_step(fastmdp_ctx *ctx, const fastmdp_state *state, double *valu
     if (terr_term) std::memcpy(terr_term, h.data() + 3 * A, A * sizeof(double));
     if (best) *best = b;
     ctx->st_pairs = s.pairs;
+    ctx->st_entries = s.entries;
     ctx->st_steps = s.steps;
     return 0;
 }
@@ -633,6 +646,7 @@ int fastmdp_plan_request(fastmdp_ctx *ctx, const fastmdp_request *req, fastmdp_p
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->st_pairs = s.pairs;
+    ctx->st_entries = s.entries;
     ctx->st_steps = s.steps;
     ctx->st_hit = s.cert_hit;
     ctx->st_miss = s.cert_miss;
@@ -667,12 +681,75 @@ int fastmdp_plan_departures(fastmdp_ctx *ctx, const fastmdp_request *req, int32_
         rc = copy_plan_out(ctx, i, hs[i], &plans[i]);
         if (rc) return rc;
         ctx->st_pairs += hs[i].pairs;
+        ctx->st_entries += hs[i].entries;
         ctx->st_steps += hs[i].steps;
         // the earliest departure whose plan reached the goal and would be accepted
         if (hs[i].status == FASTMDP_OK && hs[i].valid && (best < 0 || t0[i] < t0[best])) best = i;
     }
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     *chosen = best;
+    return 0;
+}
+
+int fastmdp_plan_batch(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, fastmdp_plan *plans) {
+    if (!ctx || n < 1 || !reqs || !plans) return FASTMDP_E_INVAL;
+    if (n > fmdp::kMaxBatch || n > ctx->max_slots) return FASTMDP_E_CAPACITY;
+    if (ctx->dc.lookahead > 1 || ctx->prop.mode != FASTMDP_PROPOSE_NONE) return FASTMDP_E_INVAL;
+    for (int i = 0; i < n; ++i) {
+        if (reqs[i].t0 < 0 || reqs[i].t0 != reqs[0].t0) return FASTMDP_E_INVAL;     // lockstep from one row
+        if (plans[i].capacity < ctx->stride || !plans[i].xyz || !plans[i].action || !plans[i].value)
+            return FASTMDP_E_CAPACITY;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    reset_stats(ctx);
+    Slot *hs = ctx->hSlots;
+    for (int i = 0; i < n; ++i) hs[i] = fresh_slot(reqs[i], i, ctx->seq);
+    HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, n * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+    const fmdp::MatePeaks mates{ctx->bs.pk, ctx->bs.owner, ctx->bs.n};
+    EvalOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    const fmdp::LaunchStop nostop{ctx->dStop, 0};
+    HIP_TRY(hipEventRecord(ctx->e0, ctx->stream));
+    // the origin checks (no step), then each step: one planner step of every
+    // aircraft still flying, then the batch's own rules and the next peaks
+    auto planner = [&](int budget) -> int {
+        hipError_t e = fmdp::launch_planner(n, fmdp::kPlanThreads, ctx->stream, ctx->dc, ctx->tb, ctx->dSlots, nullptr,
+                                            ctx->tr, budget, 0, 0, none, ctx->prop, nostop,
+                                            budget > 0 ? mates : fmdp::MatePeaks{});
+        if (e != hipSuccess) {
+            std::fprintf(stderr, "libfastmdp: planner launch failed: %s\n", hipGetErrorString(e));
+            return FASTMDP_E_DEVICE;
+        }
+        ctx->st_launches += 1;
+        return 0;
+    };
+    int rc = planner(0);
+    if (rc) return rc;
+    HIP_TRY(fmdp::launch_batch_step(ctx->dc, ctx->dSlots, n, ctx->tr, ctx->bs, 1, ctx->stream));
+    int any = 1;
+    for (int k = 0; any; ++k) {
+        rc = planner(1);
+        if (rc) return rc;
+        HIP_TRY(fmdp::launch_batch_step(ctx->dc, ctx->dSlots, n, ctx->tr, ctx->bs, 0, ctx->stream));
+        if ((k & 15) == 15 || k >= ctx->cfg.max_steps) {
+            HIP_TRY(hipMemcpyAsync(&any, ctx->bs.any, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            if (k > ctx->cfg.max_steps + 1) break;                 // every aircraft has hit the step limit
+        }
+    }
+    HIP_TRY(hipEventRecord(ctx->e1, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, n * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->e0, ctx->e1));
+    ctx->st_ms = ms;
+    for (int i = 0; i < n; ++i) {
+        rc = copy_plan_out(ctx, i, hs[i], &plans[i]);
+        if (rc) return rc;
+        ctx->st_pairs += hs[i].pairs;
+        ctx->st_entries += hs[i].entries;
+        ctx->st_steps += hs[i].steps;
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
     return 0;
 }
 
@@ -833,6 +910,7 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
                 if (done_s) done_s[r] = t_done;
                 ctx->n_plans += committed[r];
                 ctx->st_pairs += hs[s].pairs;
+                ctx->st_entries += hs[s].entries;
                 ctx->st_steps += hs[s].steps;
                 ctx->st_hit += hs[s].cert_hit;
                 ctx->st_miss += hs[s].cert_miss;
@@ -902,9 +980,10 @@ int fastmdp_table_rewind(fastmdp_ctx *ctx) {
 }
 
 int fastmdp_last_stats(const fastmdp_ctx *ctx, int64_t *pairs, int64_t *steps, int64_t *resumes, int64_t *launches,
-                       double *kernel_ms) {
+                       double *kernel_ms, int64_t *row_entries) {
     if (!ctx) return FASTMDP_E_INVAL;
     if (pairs) *pairs = ctx->st_pairs;
+    if (row_entries) *row_entries = ctx->st_entries;
     if (steps) *steps = ctx->st_steps;
     if (resumes) *resumes = ctx->st_resumes;
     if (launches) *launches = ctx->st_launches;

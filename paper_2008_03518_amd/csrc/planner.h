@@ -46,6 +46,7 @@ struct DevCfg {
     float cull_r2;                       // squared staging radius of the range query (FP32, 1 m margin)
     double max_step;                     // longest action step [m]: window point w lies within
                                          // w * max_step of the state
+    double peak_growth;                  // co-simulated batch: peak radius R_intr + peak_growth * tau
 };
 
 // Time-major structure-of-arrays known-plan table.  Entry j of row t is at
@@ -73,6 +74,7 @@ struct Slot {
     int status;       // kRunning or a FASTMDP_* plan status
     int req;          // request index (host bookkeeping)
     long long pairs;  // pair evaluations, accumulated
+    long long entries;  // table row entries read (16 bytes each), accumulated
     int steps;        // steps taken, accumulated
     int resume_at;    // FCFS check: first affected point, -1 if none
     int seq;          // sequence number: sees live table entries with own < seq
@@ -161,11 +163,40 @@ struct LaunchStop {
     int target;
 };
 
+// Peaks of the other aircraft of a co-simulated batch (Sec. V; the peak
+// table: five risk wells per aircraft along its extrapolated track): pk[4k ..
+// 4k+3] = x, y, z, radius of peak k, owner[k] its aircraft's slot, *n the
+// number of peaks (device memory, written between planner launches).
+// n == nullptr: no batch.
+constexpr int kMaxBatch = 32;       // aircraft of one co-simulated batch
+constexpr int kMatePeaks = 5;       // peaks per aircraft
+struct MatePeaks {
+    const double *pk;
+    const int *owner;
+    const int *n;
+};
+
+// Device state of a co-simulated batch between planner launches.
+struct BatchState {
+    double *pk;
+    int *owner, *n;
+    int *active;     // aircraft flying in the step just planned
+    int *prev_n;     // its point count before that step
+    int *any;        // 1 while an aircraft is flying
+};
+
 // nt: workgroup size; kPlanThreads is the one built.  prop.mode selects the
 // proposal path (FASTMDP_PROPOSE_NONE: full sweep only).
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
                           const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
-                          const PropArgs &prop, const LaunchStop &stop);
+                          const PropArgs &prop, const LaunchStop &stop, const MatePeaks &mates = MatePeaks{});
+
+// batch.hip: after each planner step of a co-simulated batch (slots 0..n-1):
+// separation between the aircraft that moved, goal capture and step limit,
+// then the peaks of the aircraft still flying for the next step.  first:
+// the launch before it only checked the origins.
+hipError_t launch_batch_step(const DevCfg &c, Slot *slots, int n, const Traj &tr, const BatchState &bs, int first,
+                             hipStream_t st);
 bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
 
 // features.hip: proposal features of n states (device arrays, see

@@ -96,6 +96,22 @@ __device__ __forceinline__ double goal_term(const DevCfg &c, double x, double y,
     return c.abs_r_goal * exp(c.log_gamma * (sqrt(ex * ex + ey * ey + ez * ez) / c.ell));
 }
 
+// Largest risk well, at point (x, y, z), of the peaks of the other aircraft
+// of a co-simulated batch (all but slot `self`): |r_intr| gamma_intr^(d/ell)
+// of the nearest peak whose radius contains the point (the wells share r and
+// gamma, so the nearest such peak gives the largest), 0 if none.
+__device__ double mate_well(const DevCfg &c, const MatePeaks &mp, int nm, int self, double x, double y, double z) {
+    double best = INFINITY;
+    for (int k = 0; k < nm; ++k) {
+        if (mp.owner[k] == self) continue;
+        const double *p = mp.pk + 4 * k;
+        const double dx = x - p[0], dy = y - p[1], dz = z - p[2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < p[3] * p[3]) best = fmin(best, d2);
+    }
+    return best < INFINITY ? c.abs_r_intr * exp(c.log_gamma_intr * (sqrt(best) / c.ell)) : 0.0;
+}
+
 // Squared distance from action a's successor to the nearest plan, from the
 // sweep's minimum m of |q|^2 - 2 Delta . q over the staged plans.
 template <int NC, int NV>
@@ -170,7 +186,7 @@ struct PlanGeom {
 template <int NT, int NC, int NV, int ZC, bool PROP, bool LOOK = false, bool CULL = false>
 __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list,
                                                      Traj tr, int budget, int validate, int epoch, EvalOut ev,
-                                                     PropArgs prop, LaunchStop stop) {
+                                                     PropArgs prop, LaunchStop stop, MatePeaks mates) {
     using Geo = PlanGeom<NT>;
     constexpr int NW = Geo::NW, TILE = Geo::TILE, PRE = Geo::PRE, PRE4 = Geo::PRE4;
     constexpr int KMAX = FASTMDP_MAX_TOPK, HID = FASTMDP_MLP_HIDDEN;
@@ -219,8 +235,10 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     const int slot = slot_list ? slot_list[blockIdx.x] : (int)blockIdx.x;
     Slot &S = slots[slot];
     const bool eval = ev.V != nullptr || ev.best != nullptr;
+    if (!eval && S.status != kRunning) return;          // a finished request (uniform: one slot per workgroup)
 
     const int H = cfg.n_head, A = cfg.n_actions;
+    const int n_mates = (!PROP && !LOOK && mates.n) ? *mates.n : 0;   // co-simulated batch peaks
     const int n_slices = NT / H;
     const int my_h = tid % H, my_slice = tid / H;
     const bool sweeper = tid < n_slices * H;
@@ -349,12 +367,12 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             __builtin_amdgcn_global_load_lds(stop.ctr, &sStopV, 4, 0, kCachePolicyDevice);
         }
     };
-    auto stage_chunk = [&](const double s[3]) -> int {
+    auto stage_chunk = [&](const double s[3], bool cull = true) -> int {
         // wave-level compaction with ballots: entry i of this lane goes after
         // the wave's visible entries of lower i and of lower lanes at i
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of the chunk landed
         take_stop();
-        if constexpr (CULL) {
+        if (CULL && cull) {
             // range query: of the visible entries only those within the
             // staging radius of the state (farther plans cannot reach any
             // scored point's well), so the offsets come before the ballots
@@ -513,7 +531,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         st_pend = 0;
     };
 
-    long long pairs = 0;
+    long long pairs = 0, entries = 0;
     int hits = 0, misses = 0;
     int since = 1 << 30;                                         // steps since the last ranking
     // after a step that fell back, the proposal sits out `skip` steps (the
@@ -553,6 +571,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
         }
         const int row = t + 1;
         const int n_row = pre_n;
+        entries += n_row;                                 // (thread 0's count is the one kept)
         const size_t rb = (size_t)row * tb.cap;
         const bool single = n_row <= tcap;
         // entry count of the next row: it came with this row's first chunk
@@ -581,7 +600,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 // are issued, after the certificate).
                 const bool fused = !eval && !(rank && prop.mode == FASTMDP_PROPOSE_MLP);
                 if (!fused) {
-                    if (n_row > 0) n_vis = stage_chunk(s);
+                    if (n_row > 0) n_vis = stage_chunk(s, false);   // the features see every plan
                     if (!eval) {                           // next row in flight meanwhile
                         pre_n = next_count();
                         if (pre_n > 0) load_chunk(row + 1, 0);
@@ -765,13 +784,19 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                             const float zs[4] = {z4.x, z4.y, z4.z, z4.w};
 #pragma unroll
                             for (int m = 0; m < 4; ++m) {
-                                const bool vis = j + m < lim && kv4[m] < seq;
+                                bool vis = j + m < lim && kv4[m] < seq;
                                 float4 p = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
                                 if (vis) {
                                     const float qx = (float)((double)xs[m] - s[0]);
                                     const float qy = (float)((double)ys[m] - s[1]);
                                     const float qz = (float)((double)zs[m] - s[2]);
                                     p = make_float4(qx, qy, cfg.zeta_scale * qz, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+                                    if constexpr (CULL) {        // range query: farther plans read as far
+                                        if (!(p.w < cfg.cull_r2)) {
+                                            vis = false;
+                                            p = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+                                        }
+                                    }
                                 }
                                 pe[gi * 4 + m] = p;
                                 seen_w += __popcll(__ballot(vis));
@@ -1011,6 +1036,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (tid == 0) {
                     st_seenw[w - 1] = nw;
                     pairs += (long long)A * nvis_w;
+                    if (w > 1) entries += nw;
                 }
                 lds_barrier();                                   // the tile becomes the partials
                 if (sweeper) {
@@ -1196,6 +1222,15 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
             Scored myr{};
             double myV = -INFINITY;
             bool myband = false;
+            // a co-simulated batch: the other aircraft's wells at this
+            // action's successor
+            double myM = 0.0;
+            if (n_mates > 0 && a < A) {
+                const int h = a / (NC * NV);
+                double x, y, z;
+                successor(cfg, at, a, s, sCos[h], sSin[h], x, y, z);
+                myM = mate_well(cfg, mates, n_mates, slot, x, y, z);
+            }
             if (a < A) {
                 // eight independent chains, so that eight LDS reads are in
                 // flight instead of one
@@ -1228,6 +1263,8 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 } else {
                     const int h = a / (NC * NV);
                     myr = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], d2);
+                    if (n_mates > 0 && myr.V > -INFINITY)       // the batch's wells join the penalties
+                        myr.V = myr.G - fmax(fmax(myr.I, myM), myr.T);
                     myV = myr.V;
                 }
             }
@@ -1249,6 +1286,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
                 if (myband) {
                     const int h = a / (NC * NV);
                     myr = score_action(cfg, tb, at, a, s, g, sCos[h], sSin[h], sD2[a]);
+                    if (n_mates > 0 && myr.V > -INFINITY) myr.V = myr.G - fmax(fmax(myr.I, myM), myr.T);
                     myV = myr.V;
                 }
                 wv = wave_max(myV);
@@ -1372,6 +1410,7 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     }
     if (tid == 0) {
         S.pairs += pairs;
+        S.entries += entries;
         S.steps += steps_here;
         S.cert_hit += hits;
         S.cert_miss += misses;
@@ -1384,33 +1423,36 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
 template <int NC, int NV, int ZC>
 static hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
                            const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
-                           const PropArgs &prop, const LaunchStop &stop) {
+                           const PropArgs &prop, const LaunchStop &stop, const MatePeaks &mates) {
     (void)nt;
     if (c.lookahead > 1 && c.range_query)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false, true, true>), dim3(nblk),
-                           dim3(kPlanThreads), 0, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+                           dim3(kPlanThreads), 0, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop, mates);
     else if (c.lookahead > 1)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false, true>), dim3(nblk), dim3(kPlanThreads), 0,
-                           st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+                           st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop, mates);
     else if (prop.mode == FASTMDP_PROPOSE_NONE && c.range_query)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false, false, true>), dim3(nblk),
-                           dim3(kPlanThreads), 0, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+                           dim3(kPlanThreads), 0, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop, mates);
     else if (prop.mode == FASTMDP_PROPOSE_NONE)
         hipLaunchKernelGGL((planner_kernel<kPlanThreads, NC, NV, ZC, false>), dim3(nblk), dim3(kPlanThreads), 0, st, c,
-                           t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+                           t, s, list, tr, budget, validate, epoch, ev, prop, stop, mates);
+    else if (c.range_query)
+        hipLaunchKernelGGL((planner_kernel<kPropThreads, NC, NV, ZC, true, false, true>), dim3(nblk),
+                           dim3(kPropThreads), 0, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop, mates);
     else
         hipLaunchKernelGGL((planner_kernel<kPropThreads, NC, NV, ZC, true>), dim3(nblk), dim3(kPropThreads), 0, st, c,
-                           t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+                           t, s, list, tr, budget, validate, epoch, ev, prop, stop, mates);
     return hipGetLastError();
 }
 
 #define FMDP_SHAPE(NC, NV, ZC) \
     if (c.n_climb == NC && c.n_speed == NV && zc == ZC) \
-        return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop);
+        return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, ev, prop, stop, mates);
 
 hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
                           const int *list, const Traj &tr, int budget, int validate, int epoch, const EvalOut &ev,
-                          const PropArgs &prop, const LaunchStop &stop) {
+                          const PropArgs &prop, const LaunchStop &stop, const MatePeaks &mates) {
     const int zc = c.zero_climb;
     if (prop.mode != FASTMDP_PROPOSE_NONE && (prop.k < 1 || prop.k > FASTMDP_MAX_TOPK || prop.k > c.n_actions))
         return hipErrorInvalidValue;

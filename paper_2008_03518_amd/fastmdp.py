@@ -49,6 +49,7 @@ class _Config(C.Structure):
         ("max_slots", C.c_int32), ("steps_per_launch", C.c_int32), ("planner_threads", C.c_int32),
         ("tie_rel", C.c_double),
         ("lookahead", C.c_int32), ("range_query", C.c_int32),
+        ("peak_growth", C.c_double),
     ]
 
 
@@ -82,12 +83,13 @@ def _load_lib():
     lib.fastmdp_plan_request.argtypes = [P, C.POINTER(_Request), C.POINTER(_Plan)]
     lib.fastmdp_commit_plan.argtypes = [P, C.POINTER(_Plan)]
     lib.fastmdp_plan_departures.argtypes = [P, C.POINTER(_Request), I32, ip, C.POINTER(_Plan), ip]
+    lib.fastmdp_plan_batch.argtypes = [P, I32, C.POINTER(_Request), C.POINTER(_Plan)]
     lib.fastmdp_num_plans.argtypes = [P]
     lib.fastmdp_plan_fcfs.argtypes = [P, I32, C.POINTER(_Request), dp, C.POINTER(_Plan), ip, dp]
     lib.fastmdp_table_snapshot.argtypes = [P]
     lib.fastmdp_table_rewind.argtypes = [P]
     lib.fastmdp_last_stats.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64),
-                                       C.POINTER(D)]
+                                       C.POINTER(D), C.POINTER(I64)]
     lib.fastmdp_save_table.argtypes = [P, C.c_char_p]
     lib.fastmdp_load_table.argtypes = [P, C.c_char_p]
     lib.fastmdp_strerror.argtypes = [C.c_int]
@@ -121,7 +123,8 @@ _lib = _load_lib()
 EXPORTS = [
     "fastmdp_create", "fastmdp_destroy", "fastmdp_set_stream", "fastmdp_load_plans", "fastmdp_load_plans_noalloc",
     "fastmdp_set_terrain",
-    "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_plan_departures", "fastmdp_commit_plan",
+    "fastmdp_eval_step", "fastmdp_plan_request", "fastmdp_plan_departures", "fastmdp_plan_batch",
+    "fastmdp_commit_plan",
     "fastmdp_num_plans", "fastmdp_plan_fcfs",
     "fastmdp_last_stats", "fastmdp_save_table", "fastmdp_load_table", "fastmdp_strerror",
     "fastmdp_table_snapshot", "fastmdp_table_rewind",
@@ -262,6 +265,7 @@ def make_config(cfg, max_slots: int = 1, tie_rel: float = TIE_REL, steps_per_lau
     c.tie_rel = float(tie_rel)
     c.lookahead = int(getattr(cfg, "lookahead", 1))
     c.range_query = int(getattr(cfg, "range_query", 0))
+    c.peak_growth = float(getattr(cfg, "peak_growth", 10.0))
     return c
 
 
@@ -412,6 +416,20 @@ class Context:
             plans[k].c = parr[k]
         return plans, int(chosen[0])
 
+    def plan_batch(self, requests, limit: Optional[int] = None):
+        """Plan the requests as one co-simulated batch (nothing committed)."""
+        m = requests.n if limit is None else min(limit, requests.n)
+        reqa = _request_array(requests, m)
+        plans = [Plan(self.capacity) for _ in range(m)]
+        parr = (_Plan * max(m, 1))()
+        for k in range(m):
+            parr[k] = plans[k].c
+        _check("fastmdp_plan_batch", _lib.fastmdp_plan_batch(self._h, m, reqa.ctypes.data_as(C.POINTER(_Request)),
+                                                             parr))
+        for k in range(m):
+            plans[k].c = parr[k]
+        return plans
+
     def commit_plan(self, plan: Plan) -> bool:
         """True if appended; False if refused for a separation/terrain conflict."""
         rc = _lib.fastmdp_commit_plan(self._h, C.byref(plan.c))
@@ -472,8 +490,11 @@ class Context:
     def stats(self) -> dict:
         v = [C.c_int64() for _ in range(4)]
         ms = C.c_double()
-        _check("fastmdp_last_stats", _lib.fastmdp_last_stats(self._h, *[C.byref(x) for x in v], C.byref(ms)))
-        return dict(pairs=v[0].value, steps=v[1].value, resumes=v[2].value, launches=v[3].value, kernel_ms=ms.value)
+        ent = C.c_int64()
+        _check("fastmdp_last_stats", _lib.fastmdp_last_stats(self._h, *[C.byref(x) for x in v], C.byref(ms),
+                                                             C.byref(ent)))
+        return dict(pairs=v[0].value, steps=v[1].value, resumes=v[2].value, launches=v[3].value, kernel_ms=ms.value,
+                    row_entries=ent.value)
 
     # -- learned action proposal ------------------------------------------
     def next_seq(self) -> int:

@@ -56,6 +56,7 @@ class Config:
     max_rows: int = 3601         # time rows in the table
     lookahead: int = 1           # steps W of the scoring window (Alg. 1 forward projections)
     range_query: int = 0         # 1: sweep only the plans within reach of the state (exact)
+    peak_growth: float = 10.0    # co-simulated batch: peak radius R_intr + peak_growth * tau [m/s]
 
     @property
     def n_climb(self) -> int:

@@ -108,3 +108,36 @@ def test_range_query_window_fcfs(fm):
     for a, b in zip(p1, p2):
         assert a.status == b.status and np.array_equal(a.points(), b.points())
         assert np.array_equal(a.values(), b.values())
+
+
+def test_range_query_with_proposal(fm):
+    """The proposal path with the range query (its k-action sweep and its
+    full-sweep fallbacks see only the plans within reach; ranking steps of a
+    network still stage every plan for the features): plans equal to the
+    full sweep's bit for bit, with the goal ranking and with a network; the
+    single-step features and ranking are those without the range query."""
+    from paper_2008_03518_amd import proposal as PR
+    sc = S.large_actions(seed=2, n_plans=3000, n_requests=300)
+    A = sc.cfg.n_actions
+    net = fm.Mlp(A)
+    net.set_params(PR.init_params(A, seed=3))
+    rs = _ranged(sc)
+    with fm.context_for(sc, max_slots=1024, steps_per_launch=512) as ctx:
+        ref, com, _ = ctx.plan_fcfs(sc.requests)
+        s0, g0 = sc.requests.origin[0], sc.requests.goal[0]
+        ctx.set_proposal(fm.PROPOSE_MLP, 8, net, 64)
+        e_full = ctx.eval_proposal(s0, g0, 0)
+    with fm.context_for(rs, max_slots=1024, steps_per_launch=512) as ctx:
+        ctx.snapshot()
+        for mode, nt in ((fm.PROPOSE_GOAL, None), (fm.PROPOSE_MLP, net)):
+            ctx.rewind()
+            ctx.set_proposal(mode, 8, nt, 64)
+            plans, c2, _ = ctx.plan_fcfs(rs.requests)
+            _log(f"[range query + proposal {mode}] {ctx.stats()}, {ctx.proposal_stats()}")
+            assert np.array_equal(c2, com)
+            for q, (a, b) in enumerate(zip(ref, plans)):
+                assert a.status == b.status and np.array_equal(a.points(), b.points()), q
+                assert np.array_equal(a.values(), b.values()), q
+        e_rq = ctx.eval_proposal(s0, g0, 0)
+    assert np.array_equal(e_full["features"], e_rq["features"]) and np.array_equal(e_full["topk"], e_rq["topk"])
+    net.close()

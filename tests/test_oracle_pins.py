@@ -592,3 +592,58 @@ def test_range_query_changes_no_value(W):
         c = too_small.eval_step(s, g, t)
         differs += int(not np.array_equal(a["I"], c["I"]))
     assert differs > 5
+
+
+# ---------------------------------------------------------------------------
+# Co-simulated batch (Sec. V; Table "Peaks created in the environment": five
+# risk wells per other aircraft at p + v*tau, tau in {-5, 0, 5, 10, 15} s,
+# radius R + 10*tau; "Build peaks"; "Process negative rewards").
+# ---------------------------------------------------------------------------
+def test_batch_of_one_is_the_single_plan():
+    sc = S.small(seed=5, n_plans=120, n_requests=3)
+    orc = Oracle(sc.cfg, sc.plans)
+    for q in range(3):
+        p = orc.plan(sc.requests.origin[q], sc.requests.goal[q], 0)
+        b = orc.plan_batch(sc.requests.origin[q:q + 1], sc.requests.goal[q:q + 1], 0)[0]
+        assert b.status == p.status and np.array_equal(b.xyz, p.xyz) and np.array_equal(b.action, p.action)
+        assert np.array_equal(b.value, p.value)
+
+
+def test_batch_head_on_pair():
+    """Two aircraft fly head-on along y = 5000 m (origins 2 km apart, each
+    one's goal the other's origin, no known plans).  Both fly straight until
+    the other's tau = 15 s peak -- 600 m ahead of it, radius 150 + 150 =
+    300 m -- reaches the straight successor: with both at 40 m/s that gap is
+    2000 - 600 - 40 - 80k m at step k, first below 300 m at k = 14, so
+    points 1..14 are straight and point 15 turns away.  Every later point
+    mirrors the other aircraft's through the midpoint (the action set is
+    relative to the goal bearing, so the pair is point-symmetric)."""
+    cfg = S.cfg_small()
+    o = np.array([[1000.0, 5000.0, 300.0], [3000.0, 5000.0, 300.0]])
+    g = o[::-1].copy()
+    a, b = Oracle(cfg).plan_batch(o, g, 0)
+    assert np.allclose(a.xyz[:15, 0], 1000.0 + 40.0 * np.arange(15), rtol=0, atol=1e-9)
+    assert np.max(np.abs(a.xyz[:15, 1] - 5000.0)) < 1e-9
+    assert abs(a.xyz[15, 1] - 5000.0) > 1.0
+    n = min(a.n_points, b.n_points)
+    mid = np.array([2000.0, 5000.0, 300.0])
+    assert np.allclose(a.xyz[:n, :2] - mid[:2], -(b.xyz[:n, :2] - mid[:2]), rtol=0, atol=1e-6)
+    assert a.status == b.status == 0 and a.n_points == b.n_points
+    # they keep R_sep apart at every common row
+    assert np.min(np.linalg.norm(a.xyz[:n] - b.xyz[:n], axis=1)) >= cfg.R_sep
+    # without each other (planned alone) both fly the straight track
+    solo = Oracle(cfg).plan(o[0], g[0], 0)
+    assert np.max(np.abs(solo.xyz[:, 1] - 5000.0)) < 1e-9
+
+
+def test_batch_far_apart_equals_solo():
+    """Aircraft whose tracks stay kilometres apart do not see each other's
+    wells: each batch plan equals the plan of the aircraft alone."""
+    cfg = S.cfg_small()
+    o = np.array([[1000.0, 1000.0, 300.0], [1000.0, 9000.0, 300.0]])
+    g = np.array([[9000.0, 1000.0, 300.0], [9000.0, 9000.0, 300.0]])
+    orc = Oracle(cfg)
+    batch = orc.plan_batch(o, g, 0)
+    for i in range(2):
+        solo = orc.plan(o[i], g[i], 0)
+        assert np.array_equal(batch[i].xyz, solo.xyz) and batch[i].status == solo.status
