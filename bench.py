@@ -44,8 +44,8 @@ ROW_ENTRY_BYTES = 16                # one table row entry read by a step: x, y, 
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "planner.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "f1286343271a72eabc00b4f553382b56f579ff566382c44bbeff2dac9ae85dfd"
-TRAFFIC_BYTES_PER_LAUNCH = {"proposal": 8.95e8, "full_sweep": 4.00e8}
+TRAFFIC_SHA256 = "942b30834c9383a75fedd506fb05f58d0d589a38f3db2fe4268c5339ae91907b"
+TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 4.66e8, "proposal": 8.66e8, "full_sweep": 4.10e8}
 
 
 def _traffic(leg: str):
