@@ -1,14 +1,16 @@
 """Build libfastmdp.so (HIP, gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["api.hip", "planner.hip", "table.hip", "batch.hip", "features.hip", "mlp.hip", "devmem.hip"]
+SOURCES = ["api.hip", "planner.hip", "range.hip", "table.hip", "batch.hip", "features.hip", "mlp.hip", "devmem.hip"]
 LIB = os.path.join(PKG, "libfastmdp.so")
 
 HIPCC_FLAGS = [
@@ -16,26 +18,42 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-value",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+_NOISE = "'-packed-fp32-ops' is not a recognized feature"
+
+
+def _run(cmd):
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in res.stderr.splitlines() if _NOISE not in l)
+    return res.returncode, err
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_2008_03518_amd/libfastmdp.so."""
+    """Compile every HIP source (one hipcc per source, in parallel) and link
+    paper_2008_03518_amd/libfastmdp.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", LIB + ".tmp"]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "'-packed-fp32-ops' is not a recognized feature"
-    err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
-    if verbose and err.strip():
-        print(err, file=sys.stderr)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="fastmdp_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[hipcc, *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        workers = max(1, min(len(cmds), os.cpu_count() or 1))
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            results = list(ex.map(_run, cmds))
+        errs = []
+        for s, (rc, err) in zip(SOURCES, results):
+            if rc != 0:
+                errs.append(f"{s}: hipcc failed ({rc}):\n{err}")
+            elif verbose and err.strip():
+                print(err, file=sys.stderr)
+        if errs:
+            raise RuntimeError("\n".join(errs))
+        rc, err = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"])
+        if rc != 0:
+            raise RuntimeError(f"hipcc link failed ({rc}):\n{err}")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -177,9 +177,12 @@ int check_cfg(const fastmdp_config *c) {
     if (c->plan_capacity < 4 || c->plan_capacity % 4 != 0)
         return FASTMDP_E_INVAL;
     if (!(c->tie_rel >= 0.0)) return FASTMDP_E_INVAL;
-    if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads) return FASTMDP_E_INVAL;
     if (c->lookahead < 0 || c->lookahead > fmdp::kMaxLookahead) return FASTMDP_E_INVAL;
     if (c->range_query != 0 && c->range_query != 1) return FASTMDP_E_INVAL;
+    if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads &&
+        !(c->planner_threads == fmdp::kRangeThreads && c->range_query == 1 && c->lookahead <= 1 &&
+          c->n_head <= fmdp::kRangeMaxHeads))
+        return FASTMDP_E_INVAL;
     if (!(c->peak_growth >= 0.0)) return FASTMDP_E_INVAL;
     return 0;
 }
@@ -231,6 +234,13 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     // state; a plan farther than reach from all of them changes nothing
     const double rc = d.reach + d.lookahead * d.max_step + 1.0;
     d.cull_r2 = (float)(rc * rc);
+    // Box test of the range-query planner: an entry the exact test keeps has
+    // |q_x|, |q_y| < sqrt(cull_r2) (1 + 2^-23), and the FP32 offset of the
+    // box test differs from q_x by under |state| 2^-24 plus 2 |q_x| 2^-24.
+    double max_abs = 0.0;
+    for (int k = 0; k < 3; ++k) max_abs = std::max({max_abs, std::fabs(c.box_min[k]), std::fabs(c.box_max[k])});
+    d.cull_box = (float)(std::sqrt((double)d.cull_r2) * 1.001 + 1.0 + max_abs * 1e-6);
+    d.planner_threads = c.planner_threads;
 }
 
 // Adds the last planner launch's duration (its events have completed).
@@ -831,16 +841,18 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
                 }
             if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
             // plan the oldest running requests, one per compute unit (the
-            // planner's workgroups take a CU each), for up to `budget` steps: a
+            // planner's workgroups take a CU each; the range-query planner's
+            // four), for up to `budget` steps: a
             // request that waits for the next launch plans against the plans its
             // predecessors finish in this one instead of re-planning after them
             list.clear();
             for (int s = 0; s < S; ++s)
                 if (slot_req[s] >= 0 && hs[s].status == fmdp::kRunning) list.push_back(s);
-            if ((int)list.size() > ctx->n_cu) {
-                std::nth_element(list.begin(), list.begin() + ctx->n_cu, list.end(),
+            const int per_launch = ctx->n_cu * (fmdp::uses_range_planner(ctx->dc, ctx->prop.mode) ? fmdp::kRangePerCU : 1);
+            if ((int)list.size() > per_launch) {
+                std::nth_element(list.begin(), list.begin() + per_launch, list.end(),
                                  [&](int a, int b) { return hs[a].req < hs[b].req; });
-                list.resize(ctx->n_cu);
+                list.resize(per_launch);
             }
             if (list.empty() && next_commit == next_req) {
                 // idle until the next arrival

@@ -11,6 +11,9 @@ namespace fmdp {
 
 constexpr int kPlanThreads = 1024;  // planning workgroup: one request per CU, 16 wave64
 constexpr int kPropThreads = 512;   // with the proposal path: 8 wave64, twice the registers per lane
+constexpr int kRangeThreads = 256;  // range-query planner: 4 wave64, four requests per CU
+constexpr int kRangePerCU = 4;      // range-query workgroups resident per CU (LDS and registers)
+constexpr int kRangeMaxHeads = 64;  // headings the range-query planner takes (its LDS budget)
 constexpr int kMaxActions = 512;
 constexpr int kMaxPoints = 4 * 4096;  // trajectory points per request (the validation list reuses the tile)
 constexpr int kMaxHeads = 128;
@@ -47,6 +50,10 @@ struct DevCfg {
     double max_step;                     // longest action step [m]: window point w lies within
                                          // w * max_step of the state
     double peak_growth;                  // co-simulated batch: peak radius R_intr + peak_growth * tau
+    float cull_box;                      // half-width of the range-query box test on x and y: the
+                                         // staging radius plus a margin for every rounding of the
+                                         // exact test (FP32 offsets of coordinates up to max_abs)
+    int planner_threads;                 // full-sweep path: 0 (automatic), kRangeThreads, kPlanThreads
 };
 
 // Time-major structure-of-arrays known-plan table.  Entry j of row t is at
@@ -198,6 +205,27 @@ hipError_t launch_planner(int nblk, int nt, hipStream_t st, const DevCfg &c, con
 hipError_t launch_batch_step(const DevCfg &c, Slot *slots, int n, const Traj &tr, const BatchState &bs, int first,
                              hipStream_t st);
 bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
+
+// Supported (climbs, speeds, zero-climb index) shapes of the planner kernels.
+#define FMDP_PLANNER_SHAPES(X) \
+    X(1, 1, 0) X(1, 1, -1) X(1, 2, 0) X(1, 2, -1) X(1, 3, 0) X(1, 3, -1) \
+    X(2, 1, -1) X(2, 2, -1) X(2, 3, -1) \
+    X(3, 1, 1) X(3, 1, -1) X(3, 2, 1) X(3, 2, -1) X(3, 3, 1) X(3, 3, -1) \
+    X(5, 1, 2) X(5, 3, 2) X(5, 3, -1)
+
+// range.hip: the range-query planner, kRangeThreads per request and
+// kRangePerCU requests per compute unit (full sweep with the range query,
+// window W = 1, at most kRangeMaxHeads headings, no proposal, no
+// co-simulated batch, no single-step outputs).
+hipError_t launch_range_planner(int nblk, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
+                                const int *list, const Traj &tr, int budget, int validate, int epoch,
+                                const LaunchStop &stop);
+// The full-sweep launches of this configuration go to the range-query
+// planner.
+inline bool uses_range_planner(const DevCfg &c, int prop_mode) {
+    return c.range_query && c.lookahead <= 1 && prop_mode == FASTMDP_PROPOSE_NONE && c.n_head <= kRangeMaxHeads &&
+           c.planner_threads != kPlanThreads;
+}
 
 // features.hip: proposal features of n states (device arrays, see
 // fastmdp_features).
