@@ -8,15 +8,19 @@ concurrent slots, starting from the 3000-plan table (rewound between steps,
 outside the timed region), including the host transfers of requests and
 plans.  Timed legs, all committing identical plans:
   * the headline: the exact full sweep with the range query (each step
-    sweeps only the plans within reach of the state, Sec. VII), with a
-    memory-side roofline (row bytes streamed);
+    sweeps only the plans within reach of the state, Sec. VII) on the
+    range-query planner (256-thread workgroups, four requests per compute
+    unit), with a memory-side roofline (row bytes streamed); beside it the
+    same on the 1024-thread kernel (one request per compute unit);
   * the plain full sweep (every plan, every action), with its roofline
     against the FP32 vector peak;
   * the learned action proposal (trained beforehand, untimed, with the
     library's own kernels on 1M tuples from the plain planner on scenarios of
     seeds 100-109) with its exact certificate, alone and with the range
     query; ablations: goal ranking without a network, an untrained network.
-Also: p50/p99 latency of Poisson-arrival serving passes, serving on a
+Also: the planners' steady-state step rate without the FCFS order (one
+launch planning 1024 departure rows of one request), p50/p99 latency of
+Poisson-arrival serving passes, serving on a
 20000-plan table, co-simulated batches (the paper's batch-size experiment),
 lookahead windows, and the FP64 CPU oracle timed on a bounded sample.
 Printed: one JSON line.
@@ -38,12 +42,13 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 HBM_PEAK_GBPS = 8000.0              # MI355X published HBM3E bandwidth
 FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared distance
-ROW_ENTRY_BYTES = 16                # one table row entry read by a step: x, y, z, visibility
+ROW_ENTRY_BYTES = 16                # one table row entry read by a 1024-thread step: x, y, z, visibility
+RANGE_ENTRY_BYTES = 8               # one row entry read by the range-query planner's box test: x, y
 
 # HBM bytes per planner launch on this workload, from the FETCH_SIZE /
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
-TRAFFIC_SOURCES = ("planner.hip", "planner.h", "proposal.h", "wave.h")
+TRAFFIC_SOURCES = ("planner.hip", "range.hip", "planner.h", "score.h", "proposal.h", "wave.h")
 TRAFFIC_SHA256 = "942b30834c9383a75fedd506fb05f58d0d589a38f3db2fe4268c5339ae91907b"
 TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 4.66e8, "proposal": 8.66e8, "full_sweep": 4.10e8}
 
@@ -152,11 +157,12 @@ def _roofline(r, leg):
     }
 
 
-def _roofline_rows(r, leg):
+def _roofline_rows(r, leg, entry_bytes=RANGE_ENTRY_BYTES):
     """Memory-side roofline of a leg that sweeps few pairs: the table rows it
-    streams (16 bytes per row entry per step: x, y, z, visibility) per
-    planner-kernel second, against the HBM peak."""
-    achieved = ROW_ENTRY_BYTES * r["entries"] / (r["kms"] * 1e-3) / 1e9
+    streams per planner-kernel second (entry_bytes per row entry per step:
+    x and y for the range-query planner's box test, x, y, z and visibility
+    for the 1024-thread kernel), against the HBM peak."""
+    achieved = entry_bytes * r["entries"] / (r["kms"] * 1e-3) / 1e9
     return {
         "bound": "hbm",
         "achieved": achieved,
@@ -167,7 +173,7 @@ def _roofline_rows(r, leg):
         "traffic_unit": "HBM bytes per launch",
         "kernel": "planner_kernel",
         "avg_launch_ms": r["kms"] / max(r["launches"], 1),
-        "bytes_per_launch": ROW_ENTRY_BYTES * r["entries"] / max(r["launches"], 1),
+        "bytes_per_launch": entry_bytes * r["entries"] / max(r["launches"], 1),
     }
 
 
@@ -375,7 +381,8 @@ def main():
         "config": {
             "workload": f"{sc.plans.n} known plans, {A} actions (24 headings x 5 climbs x 3 speeds), "
                         f"dt 0.5 s, {reqs.n} FCFS requests, 30x30x1.5 km; exact full sweep with the range query "
-                        f"(only plans within reach of the state are swept; plans identical to the full sweep)",
+                        f"(only plans within reach of the state are swept; plans identical to the full sweep), "
+                        f"range-query planner: 256-thread workgroups, four requests per compute unit",
             "known_plans": sc.plans.n, "actions": A, "requests_per_step": reqs.n,
             "slots": args.slots, "steps_per_launch": args.steps_per_launch,
             "planner_threads": args.planner_threads,
@@ -409,6 +416,36 @@ def main():
         "value": rp["value"], "ms_per_step": rp["ms_per_step"], "identical_to_full_sweep": bool(same),
         "certified_step_rate": cert_rate(rp), "pairs_swept_per_step": rp["pairs"] / len(rp["times"])}
     log(f"proposal + range query: {rp['value']:.0f} req/s, identical to the full sweep: {same}")
+
+    # the range query on the 1024-thread kernel (one request per compute unit)
+    r1 = fm.context_for(rsc, max_slots=args.slots, steps_per_launch=args.steps_per_launch, planner_threads=1024)
+    r1.snapshot()
+    rq1 = _leg(r1, reqs, fm.PROPOSE_NONE, None, args.top_k, args.steps, args.warmup, "range query, 1024 threads")
+    out["range_query_1024_threads"] = {
+        "value": rq1["value"], "ms_per_step": rq1["ms_per_step"], "planner_steps": rq1["steps"],
+        "resumes": rq1["resumes"],
+        "identical_to_full_sweep": bool(_same_plans(rq1["plans"], full["plans"])
+                                        and np.array_equal(rq1["committed"], full["committed"])),
+        "roofline": _roofline_rows(rq1, "range_query_1024", ROW_ENTRY_BYTES)}
+    # the planners alone, without the FCFS order: one launch planning request
+    # 3 from 1024 departure rows at once (every CU busy), planner steps per us
+    out["kernel_steady_state"] = {}
+    for name, kctx in (("range_query_planner", rctx), ("range_query_1024_threads", r1), ("full_sweep", ctx)):
+        kctx.set_proposal(fm.PROPOSE_NONE, 1, None, 1)
+        kctx.rewind()
+        o3, g3 = sc.requests.origin[3], sc.requests.goal[3]
+        kctx.plan_departures(o3, g3, list(range(min(1024, args.slots))))
+        kctx.plan_departures(o3, g3, list(range(min(1024, args.slots))))
+        kst = kctx.stats()
+        out["kernel_steady_state"][name] = {"plans": min(1024, args.slots), "planner_ms": kst["kernel_ms"],
+                                            "steps": kst["steps"],
+                                            "steps_per_us": kst["steps"] / (kst["kernel_ms"] * 1e3)}
+        if name == "full_sweep":
+            out["kernel_steady_state"][name]["fp32_frac"] = (FLOPS_PER_PAIR * kst["pairs"] / (kst["kernel_ms"] * 1e-3)
+                                                             / 1e12 / FP32_VECTOR_PEAK_TFLOPS)
+        log(f"steady state {name}: {kst['steps']} steps in {kst['kernel_ms']:.2f} ms")
+        kctx.rewind()
+    r1.close()
 
     if args.ablations:
         goal = _leg(ctx, reqs, fm.PROPOSE_GOAL, None, args.top_k, args.steps, 0, "goal-ranked", args.refresh)

@@ -158,7 +158,10 @@ def test_rows_of_several_chunks(fm):
 @pytest.mark.parametrize("n_head,climb,speed", [(34, (-5.0, -2.5, 0.0, 2.5, 5.0), (20.0, 30.0, 40.0)),
                                                  (128, (-5.0, 0.0, 5.0), (30.0,))])
 def test_largest_action_sets(fm, n_head, climb, speed):
-    """510 and 384 actions (two actions on most threads)."""
+    """510 actions (two actions on most threads of the range-query planner)
+    and 128 headings x 3 climbs (384 actions: more headings than the
+    range-query planner takes, so the range query runs on the 1024-thread
+    kernel)."""
     sc = S.small(seed=21, n_plans=200, n_requests=10)
     sc.cfg.n_head, sc.cfg.climb, sc.cfg.speed = n_head, climb, speed
     sc.cfg.plan_capacity = 512
@@ -248,3 +251,6 @@ def test_config_rejects_256_without_range_query(fm):
     cfg.lookahead = 1
     with fm.Context(cfg, planner_threads=256) as ctx:
         assert ctx.n_plans == 0
+    cfg.n_head = 65                                          # beyond the range-query planner's headings
+    with pytest.raises(fm.FastMDPError):
+        fm.Context(cfg, planner_threads=256)
