@@ -49,8 +49,8 @@ RANGE_ENTRY_BYTES = 8               # one row entry read by the range-query plan
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "range.hip", "planner.h", "score.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "942b30834c9383a75fedd506fb05f58d0d589a38f3db2fe4268c5339ae91907b"
-TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 4.66e8, "proposal": 8.66e8, "full_sweep": 4.10e8}
+TRAFFIC_SHA256 = "1284daaa3c5f3555e50c226482697afadd0c4079d0e3c4f507df7b85573d10b7"
+TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 6.51e8, "range_query_1024": 4.65e8, "proposal": 8.67e8, "full_sweep": 3.74e8}
 
 
 def _traffic(leg: str):
