@@ -40,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X published FP64 vector peak
 HBM_PEAK_GBPS = 8000.0              # MI355X published HBM3E bandwidth
 FLOPS_PER_PAIR = 8                  # 3 sub + 3 mul + 2 add for one squared distance
 ROW_ENTRY_BYTES = 16                # one table row entry read by a 1024-thread step: x, y, z, visibility
@@ -50,18 +51,43 @@ RANGE_ENTRY_BYTES = 8               # one row entry read by the range-query plan
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "range.hip", "planner.h", "score.h", "proposal.h", "wave.h")
 TRAFFIC_SHA256 = "1284daaa3c5f3555e50c226482697afadd0c4079d0e3c4f507df7b85573d10b7"
+# VALU counters per planner launch of an FCFS pass (profiles/planner_valu__*.md),
+# valid for the same sources: the share of SIMD cycles issuing VALU work and
+# the FLOP the hardware counts (FP32 for the sweep, FP64 for the range-query
+# planner's valuation), beside the algorithmic rooflines
+VALU_COUNTERS = {"full_sweep": {"valu_busy": 0.568, "hw_fp32_flops_per_launch": 4.93e10},
+                 "range_query": {"valu_busy": 0.106, "hw_fp64_flops_per_launch": 3.67e9}}
 TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 6.51e8, "range_query_1024": 4.65e8, "proposal": 8.67e8, "full_sweep": 3.74e8}
 
 
-def _traffic(leg: str):
+def _sources_match() -> bool:
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2008_03518_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest() == TRAFFIC_SHA256
+
+
+def _counters(leg: str, avg_launch_ms: float):
+    """The leg's VALU counter figures, or None when the sources changed."""
+    c = VALU_COUNTERS.get(leg)
+    if c is None or not _sources_match():
+        return None
+    out = {"valu_busy": c["valu_busy"]}
+    if "hw_fp32_flops_per_launch" in c:
+        out["hw_fp32_tflops"] = c["hw_fp32_flops_per_launch"] / (avg_launch_ms * 1e-3) / 1e12
+        out["hw_fp32_frac"] = out["hw_fp32_tflops"] / FP32_VECTOR_PEAK_TFLOPS
+    if "hw_fp64_flops_per_launch" in c:
+        out["hw_fp64_tflops"] = c["hw_fp64_flops_per_launch"] / (avg_launch_ms * 1e-3) / 1e12
+        out["hw_fp64_frac"] = out["hw_fp64_tflops"] / FP64_VECTOR_PEAK_TFLOPS
+    return out
+
+
+def _traffic(leg: str):
     if leg not in TRAFFIC_BYTES_PER_LAUNCH:
         return None
-    return TRAFFIC_BYTES_PER_LAUNCH[leg] if h.hexdigest() == TRAFFIC_SHA256 else None
+    return TRAFFIC_BYTES_PER_LAUNCH[leg] if _sources_match() else None
 
 
 def log(msg):
@@ -154,6 +180,7 @@ def _roofline(r, leg):
         "kernel": "planner_kernel",
         "avg_launch_ms": r["kms"] / max(r["launches"], 1),
         "flops_per_launch": FLOPS_PER_PAIR * r["pairs"] / max(r["launches"], 1),
+        "counters": _counters(leg, r["kms"] / max(r["launches"], 1)),
     }
 
 
@@ -174,6 +201,7 @@ def _roofline_rows(r, leg, entry_bytes=RANGE_ENTRY_BYTES):
         "kernel": "planner_kernel",
         "avg_launch_ms": r["kms"] / max(r["launches"], 1),
         "bytes_per_launch": entry_bytes * r["entries"] / max(r["launches"], 1),
+        "counters": _counters(leg, r["kms"] / max(r["launches"], 1)),
     }
 
 
