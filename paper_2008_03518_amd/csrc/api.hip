@@ -896,7 +896,7 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             HIP_TRY(hipMemcpyAsync(ctx->dPass, ctx->hPass, pass.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
             HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dPass, (int)pass.size(), ctx->tr, dl, epoch,
-                                           ctx->stream));
+                                           dl_len, ctx->stream));
             HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipMemcpyAsync(ctx->hDl + 1, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
             // the trajectories accepted last round were gathered ahead of this

@@ -255,7 +255,7 @@ hipError_t launch_gather_traj(const Slot *slots, const int *list, int n_list, co
 // FCFS pass over the finished, not yet accepted slots in `list`:
 // tentative insert, interaction check, withdrawal (see table.hip).
 hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, const int *list, int n_list,
-                            const Traj &tr, const DeathLog &dl, int epoch, hipStream_t st);
+                            const Traj &tr, const DeathLog &dl, int epoch, int dl_len, hipStream_t st);
 // Withdraw every table entry of the listed slots owned by sequence numbers
 // from min_own on (an interrupted FCFS call).
 hipError_t launch_fcfs_abort(const DevTable &t, Slot *slots, const int *list, int n_list, const Traj &tr, int min_own,

@@ -5,6 +5,8 @@
 #include "planner.h"
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 
 namespace fmdp {
@@ -186,10 +188,12 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, 
 }
 
 // Check, part 1: withdrawn entries the request saw; the log range is split
-// over kDeadSplit workgroups per request (blockIdx.y), which fold their
-// finds into the request's first-affected-step minimum (Slot::first, opened
-// by the insert kernel).
+// over the workgroups of the request (blockIdx.y, at most kDeadSplit: one
+// per kDeadPerGroup logged deaths), which fold their finds into the
+// request's first-affected-step minimum (Slot::first, opened by the insert
+// kernel).
 constexpr int kDeadSplit = 16;
+constexpr int kDeadPerGroup = 4096;
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c, DevTable tb, Slot *slots,
                                                                        const int *list, Traj tr, DeathLog dl,
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
         const int lo = dl.start[minep + 1], hi = dl.start[epoch];
         const double rs2 = c.reach_state * c.reach_state;
         const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
-        for (int i = lo + blockIdx.y * kPassThreads + tid; i < hi; i += kPassThreads * kDeadSplit) {
+        for (int i = lo + blockIdx.y * kPassThreads + tid; i < hi; i += kPassThreads * gridDim.y) {
             const int row = dl.row[i], col = dl.col[i], e = dl.ep[i];
             const int k = row - t0;
             if (k < 0 || k >= n) continue;
@@ -228,11 +232,13 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
     if (tid == 0 && s_first != 0x7fffffff) atomicMin(&S.first, s_first);
 }
 
-// Check, part 2: added entries, kCheckPoints points of one request per
-// workgroup (blockIdx.y picks the points).  Each wave takes one point at a
-// time and its lanes read the row's new entries together; the wave stops at
-// the first entry in reach.
+// Check, part 2: added entries, kCheckPoints points of one request at a time
+// per workgroup (blockIdx.y picks the first chunk of points, then every
+// gridDim.y-th).  Each wave takes one point at a time and its lanes read
+// the row's new entries together; the wave stops at the first entry in
+// reach (its later points cannot be the first affected one).
 constexpr int kCheckPoints = 64;
+constexpr int kAddSplit = 8;
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, DevTable tb, Slot *slots,
                                                                       const int *list, Traj tr) {
@@ -241,56 +247,56 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
     Slot &S = slots[slot];
     if (S.status == kRunning) return;                        // still planning: not in this pass
     const int n = S.n_points, t0 = S.t0, q = S.seq;
-    const int k0 = blockIdx.y * kCheckPoints;
-    if (k0 >= n) return;
     const size_t base = (size_t)slot * tr.stride;
     const double r2 = c.reach * c.reach;
     constexpr int per_wave = kCheckPoints / (kPassThreads / 64);
     static_assert(per_wave <= 64, "one lane per point of the wave");
-    // the bookkeeping of the wave's points, one lane each, read at once;
-    // then only the points whose row gained entries are scanned, in order
-    const int kl = k0 + wave * per_wave + lane;
-    int lo = 0, hi = 0, top = -1;
-    if (lane < per_wave && kl < n && t0 + kl < tb.rows) {
-        hi = min(tb.rowN[t0 + kl], tb.cap);
-        lo = tr.seen[base + kl];
-        top = kl > 0 ? tr.top[base + kl] : -1;
-    }
-    uint64_t todo = __ballot(lane < per_wave && lo < hi);
-    while (todo) {                                        // wave-uniform
-        const int i = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        const int k = k0 + wave * per_wave + i;
-        const int row = t0 + k;
-        const int lo_k = __builtin_amdgcn_readlane(lo, i), hi_k = __builtin_amdgcn_readlane(hi, i);
-        const int top_k = __builtin_amdgcn_readlane(top, i);
-        const double *x = tr.xyz + (base + k) * 3;         // chosen successor (the origin for k = 0)
-        double y[3] = {x[0], x[1], x[2]};                  // largest action's successor, if different
-        if (top_k >= 0) {
-            const double *sp = tr.xyz + (base + k - 1) * 3;
-            const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
-            const double r = sqrt(bx * bx + by * by);
-            const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
-            const int h = top_k / (c.n_climb * c.n_speed);
-            const int cl = (top_k / c.n_speed) % c.n_climb;
-            const int v = top_k % c.n_speed;
-            const double th = 2.0 * M_PI * (double)h / (double)c.n_head;
-            const double c0 = cos(th), s0 = sin(th);
-            const double step = c.speed[v] * c.dt;
-            y[0] = sp[0] + step * (cb * c0 - sb * s0);
-            y[1] = sp[1] + step * (sb * c0 + cb * s0);
-            y[2] = sp[2] + c.climb[cl] * c.dt;
+    for (int k0 = blockIdx.y * kCheckPoints; k0 < n; k0 += gridDim.y * kCheckPoints) {
+        // the bookkeeping of the wave's points, one lane each, read at once;
+        // then only the points whose row gained entries are scanned, in order
+        const int kl = k0 + wave * per_wave + lane;
+        int lo = 0, hi = 0, top = -1;
+        if (lane < per_wave && kl < n && t0 + kl < tb.rows) {
+            hi = min(tb.rowN[t0 + kl], tb.cap);
+            lo = tr.seen[base + kl];
+            top = kl > 0 ? tr.top[base + kl] : -1;
         }
-        const size_t rb = (size_t)row * tb.cap;
-        int hit = 0;
-        for (int j = lo_k + lane; j < hi_k && !hit; j += 64) {
-            if (!entry_visible(tb, rb + j, q)) continue;
-            const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
-            hit = entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2;
-        }
-        if (__ballot(hit)) {
-            if (lane == 0) atomicMin(&S.first, k);
-            break;                                          // later points of this wave cannot be first
+        uint64_t todo = __ballot(lane < per_wave && lo < hi);
+        while (todo) {                                        // wave-uniform
+            const int i = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int k = k0 + wave * per_wave + i;
+            const int row = t0 + k;
+            const int lo_k = __builtin_amdgcn_readlane(lo, i), hi_k = __builtin_amdgcn_readlane(hi, i);
+            const int top_k = __builtin_amdgcn_readlane(top, i);
+            const double *x = tr.xyz + (base + k) * 3;         // chosen successor (the origin for k = 0)
+            double y[3] = {x[0], x[1], x[2]};                  // largest action's successor, if different
+            if (top_k >= 0) {
+                const double *sp = tr.xyz + (base + k - 1) * 3;
+                const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
+                const double r = sqrt(bx * bx + by * by);
+                const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
+                const int h = top_k / (c.n_climb * c.n_speed);
+                const int cl = (top_k / c.n_speed) % c.n_climb;
+                const int v = top_k % c.n_speed;
+                const double th = 2.0 * M_PI * (double)h / (double)c.n_head;
+                const double c0 = cos(th), s0 = sin(th);
+                const double step = c.speed[v] * c.dt;
+                y[0] = sp[0] + step * (cb * c0 - sb * s0);
+                y[1] = sp[1] + step * (sb * c0 + cb * s0);
+                y[2] = sp[2] + c.climb[cl] * c.dt;
+            }
+            const size_t rb = (size_t)row * tb.cap;
+            int hit = 0;
+            for (int j = lo_k + lane; j < hi_k && !hit; j += 64) {
+                if (!entry_visible(tb, rb + j, q)) continue;
+                const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
+                hit = entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2;
+            }
+            if (__ballot(hit)) {
+                if (lane == 0) atomicMin(&S.first, k);
+                return;                                         // later points of this wave cannot be first
+            }
         }
     }
 }
@@ -343,7 +349,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_window_kernel(De
     if (minep < epoch) {
         const int lo = dl.start[minep + 1], hi = dl.start[epoch];
         const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
-        for (int i = lo + blockIdx.y * kPassThreads + tid; i < hi; i += kPassThreads * kDeadSplit) {
+        for (int i = lo + blockIdx.y * kPassThreads + tid; i < hi; i += kPassThreads * gridDim.y) {
             const int row = dl.row[i], col = dl.col[i], e = dl.ep[i];
             const size_t idx = (size_t)row * tb.cap + col;
             if (tb.own[idx] >= q) continue;
@@ -602,22 +608,23 @@ hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, in
 }
 
 hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, const int *list, int n_list,
-                            const Traj &tr, const DeathLog &dl, int epoch, hipStream_t st) {
+                            const Traj &tr, const DeathLog &dl, int epoch, int dl_len, hipStream_t st) {
     if (n_list <= 0) return hipSuccess;
+    const int dead_split = std::min(kDeadSplit, std::max(1, (dl_len + kDeadPerGroup - 1) / kDeadPerGroup));
     hipLaunchKernelGGL(fcfs_insert_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr);
     if (c.lookahead > 1) {
         if (!tr.seenw) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(fcfs_check_dead_window_kernel, dim3(n_list, kDeadSplit), dim3(kPassThreads), 0, st, c, t,
+        hipLaunchKernelGGL(fcfs_check_dead_window_kernel, dim3(n_list, dead_split), dim3(kPassThreads), 0, st, c, t,
                            slots, list, tr, dl, epoch);
         hipLaunchKernelGGL(fcfs_check_add_window_kernel, dim3(n_list, (tr.stride + kCheckPoints - 1) / kCheckPoints),
                            dim3(kPassThreads), 0, st, c, t, slots, list, tr);
         hipLaunchKernelGGL(fcfs_check_finish_window_kernel, dim3(n_list), dim3(kPassThreads), 0, st, c, t, slots, list,
                            tr, epoch);
     } else {
-        hipLaunchKernelGGL(fcfs_check_dead_kernel, dim3(n_list, kDeadSplit), dim3(kPassThreads), 0, st, c, t, slots,
+        hipLaunchKernelGGL(fcfs_check_dead_kernel, dim3(n_list, dead_split), dim3(kPassThreads), 0, st, c, t, slots,
                            list, tr, dl, epoch);
-        hipLaunchKernelGGL(fcfs_check_add_kernel, dim3(n_list, (tr.stride + kCheckPoints - 1) / kCheckPoints),
-                           dim3(kPassThreads), 0, st, c, t, slots, list, tr);
+        hipLaunchKernelGGL(fcfs_check_add_kernel, dim3(n_list, kAddSplit), dim3(kPassThreads), 0, st, c, t, slots,
+                           list, tr);
         hipLaunchKernelGGL(fcfs_check_finish_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr,
                            epoch);
     }
