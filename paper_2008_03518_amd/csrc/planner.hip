@@ -1248,41 +1248,9 @@ __global__ __launch_bounds__(NT) void planner_kernel(DevCfg cfg, DevTable tb, Sl
     if (tid == 0) flush_point();
     __syncthreads();   // st_status written by thread 0 on the way out of the loop; trajectory complete
 
-    // Commit validation of a finished OK trajectory against every table
-    // entry it saw: each point as planned (FP64) must be at least R_sep from
-    // every entry of its row that existed when the row was scored, and clear
-    // of the terrain.  A point whose scored nearest-plan distance exceeds
-    // R_sep + 1 m cannot fail (the scored distance is within a small fraction
-    // of a millimetre of the exact one, and is exact near the well radius),
-    // so the exact check runs on the other points only, found in one
-    // parallel pass.  Entries appended later are the sequencer's interaction
-    // check.
+    // Commit validation (shared with the range-query planner)
     if (!eval && validate && st_status == FASTMDP_OK) {
-        const int n = st_n;
-        const double r2 = cfg.R_sep * cfg.R_sep;
-        const double clear2 = (cfg.R_sep + 1.0) * (cfg.R_sep + 1.0);
-        int *chk = reinterpret_cast<int *>(tile);         // the tile is free here; 4 * TILE >= max_steps + 1
-        if (tid == 0) st_flag = 0;
-        __syncthreads();
-        int bad = 0;
-        for (int k = tid; k < n; k += NT) {
-            const double *x = tr.xyz + (pt_base + k) * 3;
-            if (tb.terr && x[2] - terrain_height(tb, x[0], x[1]) < 0.0) bad = 1;
-            if (!(tr.nd[pt_base + k] > clear2)) chk[atomicAdd(&st_flag, 1)] = k;
-        }
-        __syncthreads();
-        const int n_chk = st_flag;
-        for (int q = 0; q < n_chk; ++q) {
-            const int k = chk[q];
-            const double *x = tr.xyz + (pt_base + k) * 3;
-            const int lim = tr.seen[pt_base + k];
-            const size_t rb = (size_t)(t0 + k) * tb.cap;
-            for (int j = tid; j < lim; j += NT)
-                if (entry_visible(tb, rb + j, seq) &&
-                    entry_d2(x[0], x[1], x[2], tb.X[rb + j], tb.Y[rb + j], tb.Z[rb + j]) < r2)
-                    bad = 1;
-        }
-        bad = __syncthreads_or(bad);
+        const int bad = __syncthreads_or(validate_points<NT / 64>(cfg, tb, tr, pt_base, t0, st_n, seq));
         if (tid == 0) S.valid = bad == 0;
     }
 

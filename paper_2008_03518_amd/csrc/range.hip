@@ -512,50 +512,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT), amdgpu_waves_per_
     if (tid == 0) flush_point();
     __syncthreads();   // the trajectory (thread 0's stores) complete for every thread
 
-    // Commit validation of a finished OK trajectory against every table
-    // entry it saw (the 1024-thread kernel's rule): each point whose scored
-    // nearest-plan distance is not above R_sep + 1 m is checked exactly in
-    // FP64 against the visible entries its step counted, and every point
-    // against the terrain; the points to check are listed one round of NT
-    // points at a time (in the tile, free here).
+    // Commit validation (shared with the 1024-thread kernel)
     if (validate && status == FASTMDP_OK) {
-        int *chk = reinterpret_cast<int *>(tile);
-        const double r2 = cfg.R_sep * cfg.R_sep;
-        const double clear2 = (cfg.R_sep + 1.0) * (cfg.R_sep + 1.0);
-        int bad = 0;
-        for (int k0 = 0; k0 < n; k0 += NT) {              // uniform
-            const int k = k0 + tid;
-            bool f = false;
-            if (k < n) {
-                const double *x = tr.xyz + (pt_base + k) * 3;
-                if (tb.terr && x[2] - terrain_height(tb, x[0], x[1]) < 0.0) bad = 1;
-                f = !(tr.nd[pt_base + k] > clear2);
-            }
-            const uint64_t fb = __ballot(f);
-            if (lane == 0) s_wsum[wave] = __popcll(fb);
-            __syncthreads();
-            int pos = 0, tot = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const int c = s_wsum[w];
-                pos += w < wave ? c : 0;
-                tot += c;
-            }
-            if (f) chk[pos + lanes_below(fb)] = k;
-            __syncthreads();
-            for (int q = 0; q < tot; ++q) {
-                const int kk = chk[q];
-                const double *x = tr.xyz + (pt_base + kk) * 3;
-                const int lim = tr.seen[pt_base + kk];
-                const size_t rbk = (size_t)(t0 + kk) * tb.cap;
-                for (int j = tid; j < lim; j += NT)
-                    if (entry_visible(tb, rbk + j, seq) &&
-                        entry_d2(x[0], x[1], x[2], tb.X[rbk + j], tb.Y[rbk + j], tb.Z[rbk + j]) < r2)
-                        bad = 1;
-            }
-            __syncthreads();                              // chk and s_wsum reused
-        }
-        bad = __syncthreads_or(bad);
+        const int bad = __syncthreads_or(validate_points<NW>(cfg, tb, tr, pt_base, t0, n, seq));
         if (tid == 0) S.valid = bad == 0;
     }
 

@@ -109,6 +109,79 @@ static __device__ Scored score_action(const DevCfg &c, const DevTable &tb, const
     return r;
 }
 
+// Commit validation of a finished OK trajectory (Sec. V: a plan enters the
+// table only if it keeps R_sep from every plan it was planned against):
+// each point as planned (FP64) must be at least R_sep from every visible
+// entry of its row that the step scoring it counted, and clear of the
+// terrain.  A point whose scored nearest-plan distance exceeds R_sep + 1 m
+// cannot fail (the scored distance is within a small fraction of a
+// millimetre of the exact one, and is exact near the well radius), so the
+// exact check runs on the other points only.  Waves work independently:
+// wave w takes points k0 + nw lane + w of each round of 64 nw points (so
+// that the consecutive points of a close approach spread over the waves)
+// and scans one flagged point's row at a time, four entries per lane and
+// load, a box of half-width R_sep (widened by 0.1 % + 1 m + 1e-6 |point|,
+// more than every FP32 rounding of the box test) picking the entries that
+// get the exact FP64 test.  Returns this thread's finding (1: the plan
+// fails); the caller reduces it over the workgroup.  Row bases are
+// multiples of the table capacity, itself a multiple of four, so every
+// four-entry group that starts below the count lies inside the row.
+template <int NW>
+__device__ int validate_points(const DevCfg &cfg, const DevTable &tb, const Traj &tr, size_t pt_base, int t0, int n,
+                               int seq) {
+    constexpr int U = 4;                                 // four-entry groups in flight per lane
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double r2 = cfg.R_sep * cfg.R_sep;
+    const double clear2 = (cfg.R_sep + 1.0) * (cfg.R_sep + 1.0);
+    int bad = 0;
+    for (int k0 = 0; k0 < n; k0 += 64 * NW) {            // uniform
+        const int k = k0 + NW * lane + wave;
+        bool f = false;
+        if (k < n) {
+            const double *x = tr.xyz + (pt_base + k) * 3;
+            if (tb.terr && x[2] - terrain_height(tb, x[0], x[1]) < 0.0) bad = 1;
+            f = !(tr.nd[pt_base + k] > clear2);
+        }
+        uint64_t fb = __ballot(f);
+        while (fb) {                                      // wave-uniform
+            const int i = __builtin_ctzll(fb);
+            fb &= fb - 1;
+            const int kk = k0 + NW * i + wave;
+            const double *x = tr.xyz + (pt_base + kk) * 3;
+            const double px = x[0], py = x[1], pz = x[2];
+            const int lim = tr.seen[pt_base + kk];
+            const size_t rb = (size_t)(t0 + kk) * tb.cap;
+            const float fx = (float)px, fy = (float)py;
+            const float vb = (float)cfg.R_sep * 1.001f + 1.0f + 1e-6f * fmaxf(fabsf(fx), fabsf(fy));
+            for (int j0 = 4 * lane; j0 < lim; j0 += 4 * 64 * U) {
+                float4 X4[U], Y4[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + 4 * 64 * u;
+                    if (j < lim) {
+                        X4[u] = *reinterpret_cast<const float4 *>(tb.X + rb + j);
+                        Y4[u] = *reinterpret_cast<const float4 *>(tb.Y + rb + j);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = j0 + 4 * 64 * u;
+                    const float xs[4] = {X4[u].x, X4[u].y, X4[u].z, X4[u].w};
+                    const float ys[4] = {Y4[u].x, Y4[u].y, Y4[u].z, Y4[u].w};
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const size_t idx = rb + j + m;
+                        if (j + m < lim && fabsf(xs[m] - fx) <= vb && fabsf(ys[m] - fy) <= vb &&
+                            entry_visible(tb, idx, seq) && entry_d2(px, py, pz, xs[m], ys[m], tb.Z[idx]) < r2)
+                            bad = 1;
+                    }
+                }
+            }
+        }
+    }
+    return bad;
+}
+
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS
 // operations, not for its outstanding global loads (a plain __syncthreads
 // fence would also drain the prefetch of the next row).  Global data written
