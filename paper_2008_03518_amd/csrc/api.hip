@@ -86,6 +86,8 @@ struct fastmdp_ctx {
     int *dFlag = nullptr;
     // FCFS withdrawal log
     int *dDlRow = nullptr, *dDlCol = nullptr, *dDlEp = nullptr, *dDlLen = nullptr, *dDlStart = nullptr;
+    int *dDlOwn = nullptr;
+    float *dDlX = nullptr, *dDlY = nullptr;
     int dl_cap = 0, dl_start_cap = 0;
     // pinned host mirrors and the trajectory gather buffers of the FCFS engine
     Slot *hSlots = nullptr;
@@ -143,6 +145,7 @@ void free_all(fastmdp_ctx *c) {
     hipFree(c->tb.X); hipFree(c->tb.Y); hipFree(c->tb.Z); hipFree(c->tb.rowN);
     hipFree(c->tb.vis); hipFree(c->tb.own); hipFree(c->tb.dead);
     hipFree(c->dDlRow); hipFree(c->dDlCol); hipFree(c->dDlEp); hipFree(c->dDlLen); hipFree(c->dDlStart);
+    hipFree(c->dDlOwn); hipFree(c->dDlX); hipFree(c->dDlY);
     hipFree(c->dTerr);
     hipFree(c->dSlots); hipFree(c->dList); hipFree(c->dOrder); hipFree(c->dNdone);
     hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen); hipFree(c->tr.top);
@@ -423,6 +426,9 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->dDlRow, (size_t)c->dl_cap);
     rc = rc ? rc : dev_alloc(&c->dDlCol, (size_t)c->dl_cap);
     rc = rc ? rc : dev_alloc(&c->dDlEp, (size_t)c->dl_cap);
+    rc = rc ? rc : dev_alloc(&c->dDlOwn, (size_t)c->dl_cap);
+    rc = rc ? rc : dev_alloc(&c->dDlX, (size_t)c->dl_cap);
+    rc = rc ? rc : dev_alloc(&c->dDlY, (size_t)c->dl_cap);
     rc = rc ? rc : dev_alloc(&c->dDlLen, (size_t)1);
     rc = rc ? rc : dev_alloc(&c->dDlStart, (size_t)c->dl_start_cap);
     rc = rc ? rc : dev_alloc(&c->dEv, (size_t)4 * c->A);
@@ -816,7 +822,8 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
     std::vector<int> dl_start(2, 0);
     HIP_TRY(fmdp::launch_fill_int(ctx->dDlLen, 0, 1, ctx->stream));
     HIP_TRY(fmdp::launch_fill_int(ctx->dDlStart, 0, 2, ctx->stream));
-    DeathLog dl{ctx->dDlRow, ctx->dDlCol, ctx->dDlEp, ctx->dDlLen, ctx->dl_cap, ctx->dDlStart};
+    DeathLog dl{ctx->dDlRow, ctx->dDlCol, ctx->dDlEp, ctx->dDlLen, ctx->dl_cap, ctx->dDlStart,
+                ctx->dDlX, ctx->dDlY, ctx->dDlOwn};
     auto finish = [&](int rc) {
         // the device row counts include tentative and withdrawn entries
         if (hipMemcpyAsync(ctx->hRowN.data(), ctx->tb.rowN, ctx->hRowN.size() * sizeof(int), hipMemcpyDeviceToHost,

@@ -15,7 +15,7 @@ constexpr int kRangeThreads = 256;  // range-query planner: 4 wave64, four reque
 constexpr int kRangePerCU = 4;      // range-query workgroups resident per CU (LDS and registers)
 constexpr int kRangeMaxHeads = 64;  // headings the range-query planner takes (its LDS budget)
 constexpr int kMaxActions = 512;
-constexpr int kMaxPoints = 4 * 4096;  // trajectory points per request (the validation list reuses the tile)
+constexpr int kMaxPoints = 4 * 4096;  // trajectory points per request (max_steps + 1)
 constexpr int kMaxHeads = 128;
 constexpr int kMaxLookahead = 16;   // longest scoring window W (steps)
 constexpr int kRunning = -1;        // slot status while a request is being planned
@@ -123,6 +123,8 @@ struct DeathLog {
     int *len;          // device counter
     int cap;
     const int *start;  // start[e]: log length when epoch e's withdrawals began
+    float *x, *y;      // the withdrawn entry's stored x, y
+    int *own;          // and its owner (sequence number)
 };
 
 // Outputs of a single evaluated step (all device pointers, any may be null).

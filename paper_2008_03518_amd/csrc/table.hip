@@ -3,6 +3,7 @@
 // served sequencer that accepts concurrently planned trajectories strictly in
 // request order.
 #include "planner.h"
+#include "wave.h"
 
 #include <hip/hip_runtime.h>
 
@@ -191,24 +192,60 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, 
 // over the workgroups of the request (blockIdx.y, at most kDeadSplit: one
 // per kDeadPerGroup logged deaths), which fold their finds into the
 // request's first-affected-step minimum (Slot::first, opened by the insert
-// kernel).
+// kernel).  The log holds each withdrawn entry's x, y and owner, so that a
+// death is tested against the request's trajectory without reading the
+// table: first against the bounding box (in LDS) of the block of kBoxPoints
+// points holding the scored state, widened by the test radius and a margin
+// above every rounding of the FP32 box (coordinates up to 1e6 m), and only
+// inside it by the exact rule.
 constexpr int kDeadSplit = 16;
 constexpr int kDeadPerGroup = 4096;
+constexpr int kBoxPoints = 64;                              // points per bounding box: one wave's round
+constexpr int kMaxBoxes = kMaxPoints / kBoxPoints;
+static_assert(kBoxPoints == 64 && kPassThreads % 64 == 0, "a wave's points of a round form one box");
+
+// Order-preserving map of floats to ints (LDS integer minima of floats).
+__device__ __forceinline__ int ordered_key(float f) {
+    const int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float ordered_value(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c, DevTable tb, Slot *slots,
                                                                        const int *list, Traj tr, DeathLog dl,
                                                                        int epoch) {
     __shared__ int s_first, s_minep;
-    const int tid = threadIdx.x;
+    __shared__ float s_box[kMaxBoxes][4];                   // min x, max x, min y, max y
+    const int tid = threadIdx.x, lane = tid & 63;
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
     if (S.status == kRunning) return;                        // still planning: not in this pass
     const int n = S.n_points, t0 = S.t0, q = S.seq;
     const size_t base = (size_t)slot * tr.stride;
     if (tid == 0) { s_first = 0x7fffffff; s_minep = 0x7fffffff; }
-    __syncthreads();
+    // the oldest consistency epoch of the trajectory, and the boxes
     int mine = 0x7fffffff;
-    for (int k = tid; k < n; k += kPassThreads) mine = min(mine, tr.ep[base + k]);
+    for (int k0 = 0; k0 < n; k0 += kPassThreads) {          // uniform
+        const int k = k0 + tid;
+        float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+        if (k < n) {
+            mine = min(mine, tr.ep[base + k]);
+            const double *p = tr.xyz + (base + k) * 3;
+            x0 = x1 = (float)p[0];
+            y0 = y1 = (float)p[1];
+        }
+        x0 = wave_min_f32(x0);
+        x1 = wave_max_f32(x1);
+        y0 = wave_min_f32(y0);
+        y1 = wave_max_f32(y1);
+        const int b = (k - lane) / kBoxPoints;
+        if (lane == 0 && b < kMaxBoxes) {
+            s_box[b][0] = x0;
+            s_box[b][1] = x1;
+            s_box[b][2] = y0;
+            s_box[b][3] = y1;
+        }
+    }
     atomicMin(&s_minep, mine);
     __syncthreads();
     const int minep = s_minep;
@@ -216,15 +253,19 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
         const int lo = dl.start[minep + 1], hi = dl.start[epoch];
         const double rs2 = c.reach_state * c.reach_state;
         const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
+        const float rs = (float)c.reach_state + 1.0f, ro = (float)c.R_sep + 2.0f;
         for (int i = lo + blockIdx.y * kPassThreads + tid; i < hi; i += kPassThreads * gridDim.y) {
-            const int row = dl.row[i], col = dl.col[i], e = dl.ep[i];
-            const int k = row - t0;
+            const int k = dl.row[i] - t0;
+            const float ex = dl.x[i], ey = dl.y[i];
             if (k < 0 || k >= n) continue;
-            if (col >= tr.seen[base + k] || e <= tr.ep[base + k]) continue;
-            const size_t idx = (size_t)row * tb.cap + col;
-            if (tb.own[idx] >= q) continue;
+            const float *bx = s_box[(k == 0 ? 0 : k - 1) / kBoxPoints];
+            const float m = (k == 0 ? ro : rs) + 1e-6f * (fabsf(ex) + fabsf(ey));
+            if (ex < bx[0] - m || ex > bx[1] + m || ey < bx[2] - m || ey > bx[3] + m) continue;
+            const int col = dl.col[i], e = dl.ep[i];
+            if (col >= tr.seen[base + k] || e <= tr.ep[base + k] || dl.own[i] >= q) continue;
+            const size_t idx = (size_t)dl.row[i] * tb.cap + col;
             const double *sp = tr.xyz + (base + (k == 0 ? 0 : k - 1)) * 3;
-            if (entry_d2(sp[0], sp[1], sp[2], tb.X[idx], tb.Y[idx], tb.Z[idx]) < (k == 0 ? ro2 : rs2))
+            if (entry_d2(sp[0], sp[1], sp[2], ex, ey, tb.Z[idx]) < (k == 0 ? ro2 : rs2))
                 atomicMin(&s_first, k);
         }
     }
@@ -234,11 +275,16 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
 
 // Check, part 2: added entries, kCheckPoints points of one request at a time
 // per workgroup (blockIdx.y picks the first chunk of points, then every
-// gridDim.y-th).  Each wave takes one point at a time and its lanes read
-// the row's new entries together; the wave stops at the first entry in
-// reach (its later points cannot be the first affected one).
+// gridDim.y-th).  Each wave takes one point at a time; its lanes read x and
+// y of kAddLoads x 64 of the row's new entries at once and test them
+// against boxes around the point's one or two successors (half-width reach,
+// widened by a margin above every rounding of the FP32 box for coordinates
+// up to 1e6 m); only entries inside a box are read further and tested
+// exactly.  The wave stops at the first point with an entry in reach (its
+// later points cannot be the first affected one).
 constexpr int kCheckPoints = 64;
 constexpr int kAddSplit = 8;
+constexpr int kAddLoads = 4;
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, DevTable tb, Slot *slots,
                                                                       const int *list, Traj tr) {
@@ -249,6 +295,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
     const int n = S.n_points, t0 = S.t0, q = S.seq;
     const size_t base = (size_t)slot * tr.stride;
     const double r2 = c.reach * c.reach;
+    const float reach_f = (float)c.reach + 1.0f;
     constexpr int per_wave = kCheckPoints / (kPassThreads / 64);
     static_assert(per_wave <= 64, "one lane per point of the wave");
     for (int k0 = blockIdx.y * kCheckPoints; k0 < n; k0 += gridDim.y * kCheckPoints) {
@@ -286,12 +333,41 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
                 y[1] = sp[1] + step * (sb * c0 + cb * s0);
                 y[2] = sp[2] + c.climb[cl] * c.dt;
             }
+            const float ax = (float)x[0], ay = (float)x[1], bx = (float)y[0], by = (float)y[1];
+            const float m = reach_f + 1e-6f * fmaxf(fmaxf(fabsf(ax), fabsf(ay)), fmaxf(fabsf(bx), fabsf(by)));
             const size_t rb = (size_t)row * tb.cap;
             int hit = 0;
-            for (int j = lo_k + lane; j < hi_k && !hit; j += 64) {
-                if (!entry_visible(tb, rb + j, q)) continue;
-                const float px = tb.X[rb + j], py = tb.Y[rb + j], pz = tb.Z[rb + j];
-                hit = entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2;
+            for (int jb = lo_k; jb < hi_k; jb += 64 * kAddLoads) {   // uniform
+                float ex[kAddLoads], ey[kAddLoads];
+#pragma unroll
+                for (int u = 0; u < kAddLoads; ++u) {
+                    const int j = jb + 64 * u + lane;
+                    ex[u] = INFINITY;
+                    ey[u] = INFINITY;
+                    if (j < hi_k) {
+                        ex[u] = tb.X[rb + j];
+                        ey[u] = tb.Y[rb + j];
+                    }
+                }
+                bool cand[kAddLoads], any = false;
+#pragma unroll
+                for (int u = 0; u < kAddLoads; ++u) {
+                    cand[u] = (fabsf(ex[u] - ax) <= m && fabsf(ey[u] - ay) <= m) ||
+                              (fabsf(ex[u] - bx) <= m && fabsf(ey[u] - by) <= m);
+                    any = any || cand[u];
+                }
+                if (__ballot(any)) {                            // uniform; rare
+#pragma unroll
+                    for (int u = 0; u < kAddLoads; ++u) {
+                        const size_t idx = rb + jb + 64 * u + lane;
+                        if (cand[u] && entry_visible(tb, idx, q)) {
+                            const float ez = tb.Z[idx];
+                            hit |= entry_d2(x[0], x[1], x[2], ex[u], ey[u], ez) < r2 ||
+                                   entry_d2(y[0], y[1], y[2], ex[u], ey[u], ez) < r2;
+                        }
+                    }
+                    if (__ballot(hit)) break;
+                }
             }
             if (__ballot(hit)) {
                 if (lane == 0) atomicMin(&S.first, k);
@@ -491,9 +567,13 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_withdraw_kernel(DevTable tb
         tb.vis[(size_t)row * tb.cap + col] = kAlive;
         const int i = atomicAdd(dl.len, 1);
         if (i < dl.cap) {
+            const size_t idx = (size_t)row * tb.cap + col;
             dl.row[i] = row;
             dl.col[i] = col;
             dl.ep[i] = epoch;
+            dl.x[i] = tb.X[idx];
+            dl.y[i] = tb.Y[idx];
+            dl.own[i] = tb.own[idx];
         } else {
             err = 1;
         }

@@ -11,7 +11,8 @@ candidates per step: several rounds of staging and of the exact test, rows
 of four chunks); rows of ~5000 entries (three DMA chunks); the largest
 action sets (two actions per thread); a plan exactly at the well radius of
 a successor (the FP64 band recheck); short launches with Poisson arrivals
-(stop and resume); departures; degenerate requests.
+(stop and resume); departures; degenerate requests; a separation radius
+above the well radius (OK plans rejected by the commit validation).
 """
 import copy
 import os
@@ -84,6 +85,34 @@ def test_fcfs_full_size_bench_launch_config(fm):
     _log("[range planner, 3000 plans, 1000 requests]")
     out = _fcfs_all(fm, sc, max_slots=1024, steps_per_launch=512)
     assert out["range256"][2]["pairs"] < 0.01 * out["full"][2]["pairs"]
+
+
+def test_fcfs_separation_wider_than_the_well(fm):
+    """R_sep above the well radius: an OK trajectory may pass between R_intr
+    and R_sep of a plan, and only the planner's commit validation (every
+    point within R_sep + 1 m of a plan checked exactly against its row)
+    keeps it out of the table.  Every variant's FCFS acceptances equal the
+    oracle's plan-then-commit in request order, and some OK plans are
+    rejected, so the rejecting branch of the validation runs."""
+    sc = S.large_actions(seed=2, n_plans=300, n_requests=60)
+    sc.cfg.R_sep = sc.cfg.R_intr + 20.0
+    _log(f"[range planner, R_sep {sc.cfg.R_sep} > R_intr {sc.cfg.R_intr}]")
+    out = _fcfs_all(fm, sc, max_slots=1024, steps_per_launch=512)
+    plans, committed, _ = out["range256"]
+    orc = Oracle(sc.cfg, sc.plans)
+    kinds, rejected = {}, 0
+    for q in range(sc.requests.n):
+        o, g, t = sc.requests.origin[q], sc.requests.goal[q], int(sc.requests.t0[q])
+        op = orc.plan(o, g, t)
+        k = classify_trajectory(plans[q], op, orc, g)["kind"]
+        kinds[k] = kinds.get(k, 0) + 1
+        if k != "identical":
+            break                       # later requests plan against a different table
+        ok_o = op.status == fm.OK and orc.commit(op)
+        assert bool(committed[q]) == ok_o, q
+        rejected += int(op.status == fm.OK and not ok_o)
+    _log(f"  oracle kinds {kinds}, OK plans rejected by the validation: {rejected}")
+    assert kinds.get("identical", 0) >= 50 and rejected > 0 and committed.sum() > 0
 
 
 def test_sequential_with_terrain_against_oracle(fm):
