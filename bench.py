@@ -50,14 +50,14 @@ RANGE_ENTRY_BYTES = 8               # one row entry read by the range-query plan
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "range.hip", "planner.h", "score.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "1284daaa3c5f3555e50c226482697afadd0c4079d0e3c4f507df7b85573d10b7"
+TRAFFIC_SHA256 = "78339d88a88deff10de6cf1caf74e16ea50eb9bdeb7ae2397bd873cffa30b643"
 # VALU counters per planner launch of an FCFS pass (profiles/planner_valu__*.md),
 # valid for the same sources: the share of SIMD cycles issuing VALU work and
 # the FLOP the hardware counts (FP32 for the sweep, FP64 for the range-query
 # planner's valuation), beside the algorithmic rooflines
-VALU_COUNTERS = {"full_sweep": {"valu_busy": 0.568, "hw_fp32_flops_per_launch": 4.93e10},
-                 "range_query": {"valu_busy": 0.106, "hw_fp64_flops_per_launch": 3.67e9}}
-TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 6.51e8, "range_query_1024": 4.65e8, "proposal": 8.67e8, "full_sweep": 3.74e8}
+VALU_COUNTERS = {"full_sweep": {"valu_busy": 0.581, "hw_fp32_flops_per_launch": 4.77e10},
+                 "range_query": {"valu_busy": 0.147, "hw_fp64_flops_per_launch": 2.98e9}}
+TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 4.30e8, "range_query_1024": 3.78e8, "proposal": 7.14e8, "full_sweep": 3.62e8}
 
 
 def _sources_match() -> bool:
