@@ -88,6 +88,9 @@ struct fastmdp_ctx {
     int *dDlRow = nullptr, *dDlCol = nullptr, *dDlEp = nullptr, *dDlLen = nullptr, *dDlStart = nullptr;
     int *dDlOwn = nullptr;
     float *dDlX = nullptr, *dDlY = nullptr;
+    // acceptance-pass work buffers (fmdp::PassBufs)
+    int *dRowNPre = nullptr, *dInsList = nullptr, *dInsN = nullptr;
+    float4 *dBox = nullptr;
     int dl_cap = 0, dl_start_cap = 0;
     // pinned host mirrors and the trajectory gather buffers of the FCFS engine
     Slot *hSlots = nullptr;
@@ -146,6 +149,7 @@ void free_all(fastmdp_ctx *c) {
     hipFree(c->tb.vis); hipFree(c->tb.own); hipFree(c->tb.dead);
     hipFree(c->dDlRow); hipFree(c->dDlCol); hipFree(c->dDlEp); hipFree(c->dDlLen); hipFree(c->dDlStart);
     hipFree(c->dDlOwn); hipFree(c->dDlX); hipFree(c->dDlY);
+    hipFree(c->dRowNPre); hipFree(c->dInsList); hipFree(c->dInsN); hipFree(c->dBox);
     hipFree(c->dTerr);
     hipFree(c->dSlots); hipFree(c->dList); hipFree(c->dOrder); hipFree(c->dNdone);
     hipFree(c->tr.xyz); hipFree(c->tr.act); hipFree(c->tr.val); hipFree(c->tr.seen); hipFree(c->tr.top);
@@ -429,6 +433,10 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     rc = rc ? rc : dev_alloc(&c->dDlOwn, (size_t)c->dl_cap);
     rc = rc ? rc : dev_alloc(&c->dDlX, (size_t)c->dl_cap);
     rc = rc ? rc : dev_alloc(&c->dDlY, (size_t)c->dl_cap);
+    rc = rc ? rc : dev_alloc(&c->dRowNPre, (size_t)cfg->max_rows);
+    rc = rc ? rc : dev_alloc(&c->dInsList, (size_t)c->max_slots);
+    rc = rc ? rc : dev_alloc(&c->dInsN, (size_t)1);
+    rc = rc ? rc : dev_alloc(&c->dBox, (size_t)c->max_slots * fmdp::kRowBlocks);
     rc = rc ? rc : dev_alloc(&c->dDlLen, (size_t)1);
     rc = rc ? rc : dev_alloc(&c->dDlStart, (size_t)c->dl_start_cap);
     rc = rc ? rc : dev_alloc(&c->dEv, (size_t)4 * c->A);
@@ -902,8 +910,9 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             HIP_TRY(hipMemcpyAsync(ctx->dDlStart + epoch, ctx->hDl, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
             HIP_TRY(hipMemcpyAsync(ctx->dPass, ctx->hPass, pass.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
-            HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dPass, (int)pass.size(), ctx->tr, dl, epoch,
-                                           dl_len, ctx->stream));
+            const fmdp::PassBufs pbufs{ctx->dRowNPre, ctx->dInsList, ctx->dInsN, ctx->dBox};
+            HIP_TRY(fmdp::launch_fcfs_pass(ctx->dc, ctx->tb, ctx->dSlots, ctx->dPass, (int)pass.size(), ctx->tr, dl,
+                                           pbufs, epoch, dl_len, ctx->stream));
             HIP_TRY(hipMemcpyAsync(hs, ctx->dSlots, S * sizeof(Slot), hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipMemcpyAsync(ctx->hDl + 1, ctx->dDlLen, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
             // the trajectories accepted last round were gathered ahead of this

@@ -127,6 +127,19 @@ struct DeathLog {
     int *own;          // and its owner (sequence number)
 };
 
+// Work buffers of the FCFS acceptance pass: the row counts before the
+// pass's insertions, the slots whose trajectories entered entries in it, and
+// per slot the bounding box (FP32 x min, x max, y min, y max) of its points
+// in each block of kRowBlock rows, from the block of its first row on.
+constexpr int kRowBlock = 64;
+constexpr int kRowBlocks = kMaxPoints / kRowBlock + 1;   // row blocks a trajectory can touch
+struct PassBufs {
+    int *rowN_pre;     // [rows]
+    int *ins_list;     // [max_slots]
+    int *ins_n;        // [1]
+    float4 *box;       // [max_slots * kRowBlocks]
+};
+
 // Outputs of a single evaluated step (all device pointers, any may be null).
 // feat, logit, topk, cert and pbest are written only with a proposal.
 struct EvalOut {
@@ -257,7 +270,8 @@ hipError_t launch_gather_traj(const Slot *slots, const int *list, int n_list, co
 // FCFS pass over the finished, not yet accepted slots in `list`:
 // tentative insert, interaction check, withdrawal (see table.hip).
 hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, const int *list, int n_list,
-                            const Traj &tr, const DeathLog &dl, int epoch, int dl_len, hipStream_t st);
+                            const Traj &tr, const DeathLog &dl, const PassBufs &pb, int epoch, int dl_len,
+                            hipStream_t st);
 // Withdraw every table entry of the listed slots owned by sequence numbers
 // from min_own on (an interrupted FCFS call).
 hipError_t launch_fcfs_abort(const DevTable &t, Slot *slots, const int *list, int n_list, const Traj &tr, int min_own,

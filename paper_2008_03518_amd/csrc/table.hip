@@ -28,9 +28,21 @@ __device__ double table_terrain_height(const DevTable &tb, double x, double y) {
     return (1.0 - ay) * ((1.0 - ax) * h00 + ax * h10) + ay * ((1.0 - ax) * h01 + ax * h11);
 }
 
+// Order-preserving map of floats to ints (LDS integer minima of floats).
+__device__ __forceinline__ int ordered_key(float f) {
+    const int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float ordered_value(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
+
 __global__ void fill_int_kernel(int *p, int value, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = value;
+}
+
+__global__ void copy_int_kernel(int *dst, const int *src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 __global__ void scatter_points_kernel(DevTable tb, const float *pts, const int *rows, const int *cols, int n,
@@ -156,7 +168,8 @@ __global__ void commit_append_kernel(DevTable tb, const double *pts, int t0, int
 constexpr int kPassThreads = 256;
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, Slot *slots, const int *list,
-                                                                   Traj tr) {
+                                                                   Traj tr, PassBufs pb) {
+    __shared__ int s_key[kRowBlocks][4];                     // the boxes as ordered keys: x, -x, y, -y minima
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
     if (S.status == kRunning) return;                        // still planning: not in this pass
@@ -164,9 +177,10 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, 
     if (S.status != FASTMDP_OK || !S.valid) return;
     const int n = S.n_points, t0 = S.t0, own = S.seq;
     const size_t base = (size_t)slot * tr.stride;
-    int err = 0;
+    int err = 0, added = 0;
     for (int k = threadIdx.x; k < n; k += kPassThreads) {
         if (tr.col[base + k] >= 0) continue;
+        added = 1;
         const int row = t0 + k;
         if (row >= tb.rows) { err = 1; continue; }
         const int col = atomicAdd(&tb.rowN[row], 1);
@@ -186,6 +200,26 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_insert_kernel(DevTable tb, 
         tr.col[base + k] = col;
     }
     if (err) S.err = 1;
+    // a trajectory that entered entries: its row-block boxes, for the check
+    // of the entries entered in this pass
+    if (!__syncthreads_or(added) || n == 0) return;
+    const int b0 = t0 / kRowBlock, nb = (t0 + n - 1) / kRowBlock - b0 + 1;
+    for (int i = threadIdx.x; i < nb * 4; i += kPassThreads) s_key[i >> 2][i & 3] = 0x7fffffff;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += kPassThreads) {
+        const double *x = tr.xyz + (base + k) * 3;
+        const float fx = (float)x[0], fy = (float)x[1];            // the values the table stores
+        int *key = s_key[(t0 + k) / kRowBlock - b0];
+        atomicMin(&key[0], ordered_key(fx));
+        atomicMin(&key[1], ordered_key(-fx));
+        atomicMin(&key[2], ordered_key(fy));
+        atomicMin(&key[3], ordered_key(-fy));
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kPassThreads)
+        pb.box[(size_t)slot * kRowBlocks + b] = make_float4(ordered_value(s_key[b][0]), -ordered_value(s_key[b][1]),
+                                                            ordered_value(s_key[b][2]), -ordered_value(s_key[b][3]));
+    if (threadIdx.x == 0) pb.ins_list[atomicAdd(pb.ins_n, 1)] = slot;
 }
 
 // Check, part 1: withdrawn entries the request saw; the log range is split
@@ -203,13 +237,6 @@ constexpr int kDeadPerGroup = 4096;
 constexpr int kBoxPoints = 64;                              // points per bounding box: one wave's round
 constexpr int kMaxBoxes = kMaxPoints / kBoxPoints;
 static_assert(kBoxPoints == 64 && kPassThreads % 64 == 0, "a wave's points of a round form one box");
-
-// Order-preserving map of floats to ints (LDS integer minima of floats).
-__device__ __forceinline__ int ordered_key(float f) {
-    const int i = __float_as_int(f);
-    return i >= 0 ? i : i ^ 0x7fffffff;
-}
-__device__ __forceinline__ float ordered_value(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c, DevTable tb, Slot *slots,
                                                                        const int *list, Traj tr, DeathLog dl,
@@ -273,7 +300,11 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
     if (tid == 0 && s_first != 0x7fffffff) atomicMin(&S.first, s_first);
 }
 
-// Check, part 2: added entries, kCheckPoints points of one request at a time
+// Check, part 2: added entries.  Those entered before this pass (entries
+// [seen[k], rowN_pre) of row t0 + k, for each point k: the part a request
+// that was checked in the last pass no longer has) are scanned here; those
+// entered in this pass are checked trajectory against trajectory below.
+// kCheckPoints points of one request at a time
 // per workgroup (blockIdx.y picks the first chunk of points, then every
 // gridDim.y-th).  Each wave takes one point at a time; its lanes read x and
 // y of kAddLoads x 64 of the row's new entries at once and test them
@@ -286,8 +317,33 @@ constexpr int kCheckPoints = 64;
 constexpr int kAddSplit = 8;
 constexpr int kAddLoads = 4;
 
+// The successor the added-entry rule tests besides the chosen one x_k
+// (point k): the largest action's, when the step to point k chose inside
+// the tie band (top_k >= 0), else x_k itself.
+__device__ __forceinline__ void top_successor(const DevCfg &c, const Slot &S, const Traj &tr, size_t base, int k,
+                                              int top_k, double y[3]) {
+    const double *x = tr.xyz + (base + k) * 3;
+    y[0] = x[0];
+    y[1] = x[1];
+    y[2] = x[2];
+    if (top_k < 0) return;
+    const double *sp = tr.xyz + (base + k - 1) * 3;
+    const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
+    const double r = sqrt(bx * bx + by * by);
+    const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
+    const int h = top_k / (c.n_climb * c.n_speed);
+    const int cl = (top_k / c.n_speed) % c.n_climb;
+    const int v = top_k % c.n_speed;
+    const double th = 2.0 * M_PI * (double)h / (double)c.n_head;
+    const double c0 = cos(th), s0 = sin(th);
+    const double step = c.speed[v] * c.dt;
+    y[0] = sp[0] + step * (cb * c0 - sb * s0);
+    y[1] = sp[1] + step * (sb * c0 + cb * s0);
+    y[2] = sp[2] + c.climb[cl] * c.dt;
+}
+
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, DevTable tb, Slot *slots,
-                                                                      const int *list, Traj tr) {
+                                                                      const int *list, Traj tr, PassBufs pb) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
@@ -304,7 +360,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
         const int kl = k0 + wave * per_wave + lane;
         int lo = 0, hi = 0, top = -1;
         if (lane < per_wave && kl < n && t0 + kl < tb.rows) {
-            hi = min(tb.rowN[t0 + kl], tb.cap);
+            hi = min(pb.rowN_pre[t0 + kl], tb.cap);
             lo = tr.seen[base + kl];
             top = kl > 0 ? tr.top[base + kl] : -1;
         }
@@ -317,22 +373,8 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
             const int lo_k = __builtin_amdgcn_readlane(lo, i), hi_k = __builtin_amdgcn_readlane(hi, i);
             const int top_k = __builtin_amdgcn_readlane(top, i);
             const double *x = tr.xyz + (base + k) * 3;         // chosen successor (the origin for k = 0)
-            double y[3] = {x[0], x[1], x[2]};                  // largest action's successor, if different
-            if (top_k >= 0) {
-                const double *sp = tr.xyz + (base + k - 1) * 3;
-                const double bx = S.goal[0] - sp[0], by = S.goal[1] - sp[1];
-                const double r = sqrt(bx * bx + by * by);
-                const double cb = r > 0.0 ? bx / r : 1.0, sb = r > 0.0 ? by / r : 0.0;
-                const int h = top_k / (c.n_climb * c.n_speed);
-                const int cl = (top_k / c.n_speed) % c.n_climb;
-                const int v = top_k % c.n_speed;
-                const double th = 2.0 * M_PI * (double)h / (double)c.n_head;
-                const double c0 = cos(th), s0 = sin(th);
-                const double step = c.speed[v] * c.dt;
-                y[0] = sp[0] + step * (cb * c0 - sb * s0);
-                y[1] = sp[1] + step * (sb * c0 + cb * s0);
-                y[2] = sp[2] + c.climb[cl] * c.dt;
-            }
+            double y[3];                                       // largest action's successor, if different
+            top_successor(c, S, tr, base, k, top_k, y);
             const float ax = (float)x[0], ay = (float)x[1], bx = (float)y[0], by = (float)y[1];
             const float m = reach_f + 1e-6f * fmaxf(fmaxf(fabsf(ax), fabsf(ay)), fmaxf(fabsf(bx), fabsf(by)));
             const size_t rb = (size_t)row * tb.cap;
@@ -375,6 +417,103 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, 
             }
         }
     }
+}
+
+// Check, part 2b: the entries entered in this pass, trajectory against
+// trajectory.  Each entered a point of a trajectory in the pass's list of
+// inserting slots, at a column at or past the row's count before the pass.
+// The request's scored states are boxed per block of kRowBlock rows (in
+// LDS); a block of an inserted trajectory of an earlier request whose box
+// comes within reach + the longest step (+ 1 m and 1e-6 |coordinate| for
+// the FP32 boxes) of the request's box is a candidate, and a wave then
+// tests its rows, one per lane, by the added-entry rule: the entry in reach
+// of the chosen successor or of the largest action's.  Outside such blocks
+// no entry can be in reach of a successor of the request.
+constexpr int kNewCand = 4 * kPassThreads;             // (trajectory, block) pairs tested per round
+
+__global__ __launch_bounds__(kPassThreads) void fcfs_check_new_kernel(DevCfg c, DevTable tb, Slot *slots,
+                                                                      const int *list, Traj tr, PassBufs pb) {
+    __shared__ int s_key[kRowBlocks][4];                  // scored states' boxes as ordered keys
+    __shared__ float s_box[kRowBlocks][4];                // x min, x max, y min, y max
+    __shared__ int2 s_cand[kNewCand];                     // (inserting slot, block)
+    __shared__ int s_nc, s_first;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int slot = list[blockIdx.x];
+    Slot &S = slots[slot];
+    if (S.status == kRunning) return;                        // still planning: not in this pass
+    const int n_ins = *pb.ins_n;
+    const int n = S.n_points, t0 = S.t0, q = S.seq;
+    if (n_ins == 0 || n == 0) return;                        // uniform
+    const size_t base = (size_t)slot * tr.stride;
+    const int b0 = t0 / kRowBlock, nb = (t0 + n - 1) / kRowBlock - b0 + 1;
+    for (int i = tid; i < nb * 4; i += kPassThreads) s_key[i >> 2][i & 3] = 0x7fffffff;
+    if (tid == 0) {
+        s_nc = 0;
+        s_first = 0x7fffffff;
+    }
+    __syncthreads();
+    for (int k = tid; k < n; k += kPassThreads) {
+        const double *x = tr.xyz + (base + (k == 0 ? 0 : k - 1)) * 3;   // the state point k was scored from
+        const float fx = (float)x[0], fy = (float)x[1];
+        int *key = s_key[(t0 + k) / kRowBlock - b0];
+        atomicMin(&key[0], ordered_key(fx));
+        atomicMin(&key[1], ordered_key(-fx));
+        atomicMin(&key[2], ordered_key(fy));
+        atomicMin(&key[3], ordered_key(-fy));
+    }
+    __syncthreads();
+    for (int b = tid; b < nb; b += kPassThreads) {
+        s_box[b][0] = ordered_value(s_key[b][0]);
+        s_box[b][1] = -ordered_value(s_key[b][1]);
+        s_box[b][2] = ordered_value(s_key[b][2]);
+        s_box[b][3] = -ordered_value(s_key[b][3]);
+    }
+    __syncthreads();
+    const double r2 = c.reach * c.reach;
+    const float reach_f = (float)(c.reach + c.max_step) + 1.0f;
+    const int total = n_ins * nb;
+    for (int c0 = 0; c0 < total; c0 += kNewCand) {            // uniform
+        // 1. box against box
+        for (int i = c0 + tid; i < min(total, c0 + kNewCand); i += kPassThreads) {
+            const int pi = i / nb, b = i - pi * nb;
+            const int ps = pb.ins_list[pi];
+            const Slot &P = slots[ps];
+            if (P.seq >= q) continue;                          // not visible to this request
+            const int pb0 = P.t0 / kRowBlock, pnb = (P.t0 + P.n_points - 1) / kRowBlock - pb0 + 1;
+            const int bb = b0 + b - pb0;
+            if (bb < 0 || bb >= pnb) continue;
+            const float4 e = pb.box[(size_t)ps * kRowBlocks + bb];
+            const float *qb = s_box[b];
+            if (!(qb[0] <= qb[1])) continue;                   // no point of the request in this block
+            const float m = reach_f + 1e-6f * fmaxf(fmaxf(fabsf(qb[0]), fabsf(qb[1])), fmaxf(fabsf(qb[2]), fabsf(qb[3])));
+            if (e.x > qb[1] + m || e.y < qb[0] - m || e.z > qb[3] + m || e.w < qb[2] - m) continue;
+            s_cand[atomicAdd(&s_nc, 1)] = make_int2(ps, b);
+        }
+        __syncthreads();
+        // 2. the candidate blocks' rows, one per lane
+        const int nc = s_nc;
+        for (int ci = wave; ci < nc; ci += kPassThreads / 64) {
+            const int ps = s_cand[ci].x;
+            const int r = (b0 + s_cand[ci].y) * kRowBlock + lane;
+            const Slot &P = slots[ps];
+            const int k = r - t0, kp = r - P.t0;
+            if (k < 0 || k >= n || kp < 0 || kp >= P.n_points || r >= tb.rows) continue;
+            const int col = tr.col[(size_t)ps * tr.stride + kp];
+            if (col < pb.rowN_pre[r] || col >= tb.cap) continue;      // entered before this pass (or none)
+            const size_t idx = (size_t)r * tb.cap + col;
+            if (!entry_visible(tb, idx, q)) continue;
+            const double *x = tr.xyz + (base + k) * 3;
+            double y[3];
+            top_successor(c, S, tr, base, k, k > 0 ? tr.top[base + k] : -1, y);
+            const float px = tb.X[idx], py = tb.Y[idx], pz = tb.Z[idx];
+            if (entry_d2(x[0], x[1], x[2], px, py, pz) < r2 || entry_d2(y[0], y[1], y[2], px, py, pz) < r2)
+                atomicMin(&s_first, k);
+        }
+        __syncthreads();
+        if (tid == 0) s_nc = 0;
+        __syncthreads();
+    }
+    if (tid == 0 && s_first != 0x7fffffff) atomicMin(&S.first, s_first);
 }
 
 // Lookahead window W > 1: the step to point k (from point k-1 at row
@@ -688,10 +827,14 @@ hipError_t launch_commit_append(const DevTable &t, const double *pts, int t0, in
 }
 
 hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, const int *list, int n_list,
-                            const Traj &tr, const DeathLog &dl, int epoch, int dl_len, hipStream_t st) {
+                            const Traj &tr, const DeathLog &dl, const PassBufs &pb, int epoch, int dl_len,
+                            hipStream_t st) {
     if (n_list <= 0) return hipSuccess;
     const int dead_split = std::min(kDeadSplit, std::max(1, (dl_len + kDeadPerGroup - 1) / kDeadPerGroup));
-    hipLaunchKernelGGL(fcfs_insert_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr);
+    // the row counts before this pass's insertions; no slot inserted yet
+    hipLaunchKernelGGL(copy_int_kernel, dim3((t.rows + 255) / 256), dim3(256), 0, st, pb.rowN_pre, t.rowN, t.rows);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, st, pb.ins_n, 0, 1);
+    hipLaunchKernelGGL(fcfs_insert_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr, pb);
     if (c.lookahead > 1) {
         if (!tr.seenw) return hipErrorInvalidValue;
         hipLaunchKernelGGL(fcfs_check_dead_window_kernel, dim3(n_list, dead_split), dim3(kPassThreads), 0, st, c, t,
@@ -704,7 +847,8 @@ hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, con
         hipLaunchKernelGGL(fcfs_check_dead_kernel, dim3(n_list, dead_split), dim3(kPassThreads), 0, st, c, t, slots,
                            list, tr, dl, epoch);
         hipLaunchKernelGGL(fcfs_check_add_kernel, dim3(n_list, kAddSplit), dim3(kPassThreads), 0, st, c, t, slots,
-                           list, tr);
+                           list, tr, pb);
+        hipLaunchKernelGGL(fcfs_check_new_kernel, dim3(n_list), dim3(kPassThreads), 0, st, c, t, slots, list, tr, pb);
         hipLaunchKernelGGL(fcfs_check_finish_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr,
                            epoch);
     }
