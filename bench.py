@@ -10,7 +10,8 @@ plans.  Timed legs, all committing identical plans:
   * the headline: the exact full sweep with the range query (each step
     sweeps only the plans within reach of the state, Sec. VII) on the
     range-query planner (256-thread workgroups, four requests per compute
-    unit), with a memory-side roofline (row bytes streamed); beside it the
+    unit, or 512-thread workgroups, one per compute unit, for a launch that
+    holds no more requests than compute units), with a memory-side roofline (row bytes streamed); beside it the
     same on the 1024-thread kernel (one request per compute unit);
   * the plain full sweep (every plan, every action), with its roofline
     against the FP32 vector peak;
@@ -410,7 +411,8 @@ def main():
             "workload": f"{sc.plans.n} known plans, {A} actions (24 headings x 5 climbs x 3 speeds), "
                         f"dt 0.5 s, {reqs.n} FCFS requests, 30x30x1.5 km; exact full sweep with the range query "
                         f"(only plans within reach of the state are swept; plans identical to the full sweep), "
-                        f"range-query planner: 256-thread workgroups, four requests per compute unit",
+                        f"range-query planner: 256-thread workgroups, four requests per compute unit "
+                        f"(512-thread, one per compute unit, in launches of at most one request per CU)",
             "known_plans": sc.plans.n, "actions": A, "requests_per_step": reqs.n,
             "slots": args.slots, "steps_per_launch": args.steps_per_launch,
             "planner_threads": args.planner_threads,

@@ -95,12 +95,15 @@ typedef struct {
                                         1024 (one request per compute unit) or,
                                         with range_query = 1, lookahead <= 1 and
                                         n_head <= 64, 256 (four requests per
-                                        compute unit).  0
-                                        takes 256 where allowed, else 1024; the
-                                        proposal path keeps its own workgroup and
-                                        single-step outputs and co-simulated
-                                        batches the 1024-thread one.  Every
-                                        choice gives the same plans bit for bit */
+                                        compute unit) or 512 (one request per
+                                        compute unit).  0 takes, where allowed,
+                                        512 for a launch of at most one request
+                                        per compute unit and 256 for a larger
+                                        one, else 1024; the proposal path keeps
+                                        its own workgroup and single-step
+                                        outputs and co-simulated batches the
+                                        1024-thread one.  Every choice gives
+                                        the same plans bit for bit               */
     double tie_rel;                  /* argmax: values within tie_rel*|max| of the
                                         maximum tie; the lowest index wins        */
     int32_t lookahead;               /* scoring window W, 1..16 (0 reads as 1):

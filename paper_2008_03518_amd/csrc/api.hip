@@ -187,8 +187,8 @@ int check_cfg(const fastmdp_config *c) {
     if (c->lookahead < 0 || c->lookahead > fmdp::kMaxLookahead) return FASTMDP_E_INVAL;
     if (c->range_query != 0 && c->range_query != 1) return FASTMDP_E_INVAL;
     if (c->planner_threads != 0 && c->planner_threads != fmdp::kPlanThreads &&
-        !(c->planner_threads == fmdp::kRangeThreads && c->range_query == 1 && c->lookahead <= 1 &&
-          c->n_head <= fmdp::kRangeMaxHeads))
+        !((c->planner_threads == fmdp::kRangeThreads || c->planner_threads == fmdp::kRangeThreadsSolo) &&
+          c->range_query == 1 && c->lookahead <= 1 && c->n_head <= fmdp::kRangeMaxHeads))
         return FASTMDP_E_INVAL;
     if (!(c->peak_growth >= 0.0)) return FASTMDP_E_INVAL;
     return 0;
@@ -248,6 +248,7 @@ void make_devcfg(const fastmdp_config &c, DevCfg &d) {
     for (int k = 0; k < 3; ++k) max_abs = std::max({max_abs, std::fabs(c.box_min[k]), std::fabs(c.box_max[k])});
     d.cull_box = (float)(std::sqrt((double)d.cull_r2) * 1.001 + 1.0 + max_abs * 1e-6);
     d.planner_threads = c.planner_threads;
+    d.n_cu = 256;                          // the device's count is set once the context knows it
 }
 
 // Adds the last planner launch's duration (its events have completed).
@@ -488,6 +489,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
                 c->n_cu = cus;
         }
     }
+    c->dc.n_cu = c->n_cu;
     c->dScratch = noalloc_scratch(c->dev);
     if (!c->dScratch) {
         free_all(c);

@@ -13,6 +13,7 @@ constexpr int kPlanThreads = 1024;  // planning workgroup: one request per CU, 1
 constexpr int kPropThreads = 512;   // with the proposal path: 8 wave64, twice the registers per lane
 constexpr int kRangeThreads = 256;  // range-query planner: 4 wave64, four requests per CU
 constexpr int kRangePerCU = 4;      // range-query workgroups resident per CU (LDS and registers)
+constexpr int kRangeThreadsSolo = 512;  // range-query planner alone on a CU: 8 wave64, one action per thread
 constexpr int kRangeMaxHeads = 64;  // headings the range-query planner takes (its LDS budget)
 constexpr int kMaxActions = 512;
 constexpr int kMaxPoints = 4 * 4096;  // trajectory points per request (max_steps + 1)
@@ -53,7 +54,9 @@ struct DevCfg {
     float cull_box;                      // half-width of the range-query box test on x and y: the
                                          // staging radius plus a margin for every rounding of the
                                          // exact test (FP32 offsets of coordinates up to max_abs)
-    int planner_threads;                 // full-sweep path: 0 (automatic), kRangeThreads, kPlanThreads
+    int planner_threads;                 // full-sweep path: 0 (automatic), kRangeThreads, kRangeThreadsSolo,
+                                         // kPlanThreads
+    int n_cu;                            // compute units of the device
 };
 
 // Time-major structure-of-arrays known-plan table.  Entry j of row t is at
@@ -229,9 +232,10 @@ bool planner_shape_supported(int n_climb, int n_speed, int zero_climb);
     X(5, 1, 2) X(5, 3, 2) X(5, 3, -1)
 
 // range.hip: the range-query planner, kRangeThreads per request and
-// kRangePerCU requests per compute unit (full sweep with the range query,
-// window W = 1, at most kRangeMaxHeads headings, no proposal, no
-// co-simulated batch, no single-step outputs).
+// kRangePerCU requests per compute unit, or kRangeThreadsSolo per request
+// alone on a compute unit (full sweep with the range query, window W = 1,
+// at most kRangeMaxHeads headings, no proposal, no co-simulated batch, no
+// single-step outputs).
 hipError_t launch_range_planner(int nblk, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s,
                                 const int *list, const Traj &tr, int budget, int validate, int epoch,
                                 const LaunchStop &stop);
@@ -240,6 +244,13 @@ hipError_t launch_range_planner(int nblk, hipStream_t st, const DevCfg &c, const
 inline bool uses_range_planner(const DevCfg &c, int prop_mode) {
     return c.range_query && c.lookahead <= 1 && prop_mode == FASTMDP_PROPOSE_NONE && c.n_head <= kRangeMaxHeads &&
            c.planner_threads != kPlanThreads;
+}
+// Its workgroup size for a launch of nblk requests: as configured, else
+// one request per CU on kRangeThreadsSolo threads when the launch holds no
+// more requests than CUs, four per CU on kRangeThreads otherwise.
+inline int range_planner_threads(const DevCfg &c, int nblk) {
+    if (c.planner_threads == kRangeThreads || c.planner_threads == kRangeThreadsSolo) return c.planner_threads;
+    return nblk <= c.n_cu ? kRangeThreadsSolo : kRangeThreads;
 }
 
 // features.hip: proposal features of n states (device arrays, see

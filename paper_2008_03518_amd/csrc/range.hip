@@ -40,26 +40,29 @@ namespace fmdp {
 
 namespace {
 
-constexpr int NT = kRangeThreads;
-constexpr int NW = NT / 64;
 constexpr int RAW = 4096;                    // row entries per chunk (x and y in LDS)
-constexpr int G4 = RAW / (4 * NT);           // four-entry groups per lane and chunk
-constexpr int TILE = NT;                     // staged entries per round: one candidate per thread
-constexpr int APT = kMaxActions / NT;        // actions per thread
 constexpr int HMAX = kRangeMaxHeads;
-static_assert(RAW % (4 * NT) == 0, "a chunk is a whole number of four-entry groups per lane");
-static_assert(4 * G4 <= 32, "a lane's candidates of a chunk fit one 32-bit mask");
-static_assert(kMaxActions % NT == 0, "actions are dealt to threads in whole rounds");
-static_assert(HMAX <= NT, "one thread per heading");
 
 __device__ __forceinline__ int lanes_below(uint64_t bal) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
 }
 
-template <int NC, int NV, int ZC>
-__global__ __attribute__((amdgpu_flat_work_group_size(NT, NT), amdgpu_waves_per_eu(4))) void range_planner_kernel(
+// NT threads per request: kRangeThreads with kRangePerCU requests resident
+// per CU (up to 128 VGPRs each), or kRangeThreadsSolo with one per CU (no
+// register spills) for launches that hold at most one request per CU.
+template <int NT, int NC, int NV, int ZC>
+__global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
+                          amdgpu_waves_per_eu(NT == kRangeThreads ? kRangePerCU : 2))) void range_planner_kernel(
     DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list, Traj tr, int budget, int validate, int epoch,
     LaunchStop stop) {
+    constexpr int NW = NT / 64;
+    constexpr int G4 = RAW / (4 * NT);           // four-entry groups per lane and chunk
+    constexpr int TILE = NT;                     // staged entries per round: one candidate per thread
+    constexpr int APT = kMaxActions / NT;        // actions per thread
+    static_assert(RAW % (4 * NT) == 0, "a chunk is a whole number of four-entry groups per lane");
+    static_assert(4 * G4 <= 32, "a lane's candidates of a chunk fit one 32-bit mask");
+    static_assert(kMaxActions % NT == 0, "actions are dealt to threads in whole rounds");
+    static_assert(HMAX <= NT, "one thread per heading");
     __shared__ __attribute__((aligned(16))) float rawX[RAW], rawY[RAW];   // the row chunk's x, y by DMA
     __shared__ float4 tile[TILE];               // staged entries of one round; validation point list
     __shared__ double sCos[2][HMAX], sSin[2][HMAX];      // heading directions, alternate steps
@@ -529,10 +532,16 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT), amdgpu_waves_per_
 }
 
 template <int NC, int NV, int ZC>
-hipError_t launch_t(int nblk, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s, const int *list,
+hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s, const int *list,
                     const Traj &tr, int budget, int validate, int epoch, const LaunchStop &stop) {
-    hipLaunchKernelGGL((range_planner_kernel<NC, NV, ZC>), dim3(nblk), dim3(NT), 0, st, c, t, s, list, tr, budget,
-                       validate, epoch, stop);
+    if (nt == kRangeThreadsSolo)
+        hipLaunchKernelGGL((range_planner_kernel<kRangeThreadsSolo, NC, NV, ZC>), dim3(nblk), dim3(nt), 0, st, c, t,
+                           s, list, tr, budget, validate, epoch, stop);
+    else if (nt == kRangeThreads)
+        hipLaunchKernelGGL((range_planner_kernel<kRangeThreads, NC, NV, ZC>), dim3(nblk), dim3(nt), 0, st, c, t, s,
+                           list, tr, budget, validate, epoch, stop);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -543,9 +552,10 @@ hipError_t launch_range_planner(int nblk, hipStream_t st, const DevCfg &c, const
                                 const LaunchStop &stop) {
     if (!c.range_query || c.lookahead > 1 || c.n_head > kRangeMaxHeads) return hipErrorInvalidValue;
     const int zc = c.zero_climb;
+    const int nt = range_planner_threads(c, nblk);
 #define FMDP_RANGE_SHAPE(NC, NV, ZC) \
     if (c.n_climb == NC && c.n_speed == NV && zc == ZC) \
-        return launch_t<NC, NV, ZC>(nblk, st, c, t, s, list, tr, budget, validate, epoch, stop);
+        return launch_t<NC, NV, ZC>(nblk, nt, st, c, t, s, list, tr, budget, validate, epoch, stop);
     FMDP_PLANNER_SHAPES(FMDP_RANGE_SHAPE)
 #undef FMDP_RANGE_SHAPE
     return hipErrorInvalidValue;

@@ -1,5 +1,5 @@
 """The range-query planner (256-thread workgroups, four requests per compute
-unit) through the C ABI.
+unit, or 512-thread workgroups alone on a compute unit) through the C ABI.
 
 It must give the plans, actions and values of the 1024-thread range query
 and of the full sweep bit for bit (the full sweep is compared with the FP64
@@ -30,8 +30,13 @@ from paper_2008_03518_amd import scenario as S  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 # (range_query, planner_threads): the full sweep, the 1024-thread range
-# query, the range-query planner (0 selects it with the range query)
-VARIANTS = {"full": (0, 0), "range1024": (1, 1024), "range256": (1, 0)}
+# query, the range-query planner on 256-thread workgroups (four per CU), on
+# 512-thread workgroups (one per CU), and as the context picks per launch
+# (planner_threads 0: 512 threads when a launch holds at most one request
+# per CU, else 256)
+VARIANTS = {"full": (0, 0), "range1024": (1, 1024), "range256": (1, 256), "range512": (1, 512), "auto": (1, 0)}
+RANGE_VARIANTS = [v for v in VARIANTS if v != "full"]
+RANGE_MAX_HEADS = 64                # headings the range-query planner takes
 
 
 @pytest.fixture(scope="module")
@@ -64,12 +69,16 @@ def _fcfs_all(fm, sc, reqs=None, arrivals=None, **kw):
     reqs = sc.requests if reqs is None else reqs
     out = {}
     for name in VARIANTS:
+        if VARIANTS[name][1] in (256, 512) and sc.cfg.n_head > RANGE_MAX_HEADS:
+            continue                        # the range-query planner's sizes are refused (auto: 1024 threads)
         with _ctx(fm, sc, name, **kw) as ctx:
             plans, committed, _ = ctx.plan_fcfs(reqs, arrival_s=arrivals)
             out[name] = (plans, committed, ctx.stats())
         _log(f"  {name}: {out[name][2]}, committed {int(out[name][1].sum())}/{reqs.n}")
     ref_p, ref_c, _ = out["full"]
-    for name in ("range1024", "range256"):
+    for name in RANGE_VARIANTS:
+        if name not in out:
+            continue
         p, c, _ = out[name]
         assert np.array_equal(c, ref_c), name
         for q, (a, b) in enumerate(zip(ref_p, p)):
@@ -121,21 +130,24 @@ def test_sequential_with_terrain_against_oracle(fm):
     sc = S.paper_scale(seed=1, n_plans=2000, n_requests=12)
     orc = Oracle(sc.cfg, sc.plans, sc.terrain)
     kinds = {}
-    with _ctx(fm, sc, "full") as full, _ctx(fm, sc, "range256") as rq:
+    with _ctx(fm, sc, "full") as full, _ctx(fm, sc, "range256") as rq, _ctx(fm, sc, "range512") as r5:
         for q in range(sc.requests.n):
             o, g, t = sc.requests.origin[q], sc.requests.goal[q], int(sc.requests.t0[q])
             a = full.plan_request(o, g, t)
             b = rq.plan_request(o, g, t)
+            c = r5.plan_request(o, g, t)
             _same(a, b, q)
+            _same(a, c, q)
             op = orc.plan(o, g, t)
             k = classify_trajectory(b, op, orc, g)["kind"]
             kinds[k] = kinds.get(k, 0) + 1
             if op.status == fm.OK:
                 ok_o = orc.commit(op)
                 if k == "identical":
-                    assert full.commit_plan(a) == ok_o and rq.commit_plan(b) == ok_o
+                    assert full.commit_plan(a) == ok_o and rq.commit_plan(b) == ok_o and r5.commit_plan(c) == ok_o
                 else:
-                    assert full.commit_points(op.t0, op.xyz) == ok_o and rq.commit_points(op.t0, op.xyz) == ok_o
+                    assert (full.commit_points(op.t0, op.xyz) == ok_o and rq.commit_points(op.t0, op.xyz) == ok_o
+                            and r5.commit_points(op.t0, op.xyz) == ok_o)
     _log(f"[range planner, terrain] {kinds}")
     assert kinds.get("identical", 0) >= 10
 
@@ -164,7 +176,7 @@ def test_dense_shell_several_rounds(fm):
             ctx.load_plans(plans)
             res[name] = (ctx.plan_request(o, g, 0), ctx.stats())
         _log(f"[shell] {name}: status {res[name][0].status}, {res[name][0].n_points} points, {res[name][1]}")
-    for name in ("range1024", "range256"):
+    for name in RANGE_VARIANTS:
         _same(res["full"][0], res[name][0], name)
     p, st = res["range256"]
     assert p.status == fm.OK and p.n_points - 1 == int(np.ceil(1500.0 / cfg.ell - 1.0))
@@ -217,7 +229,7 @@ def test_band_recheck_at_the_well_radius(fm):
         with fm.Context(c, planner_threads=VARIANTS[name][1]) as ctx:
             ctx.load_plans(plans)
             res[name] = ctx.plan_request(o, g, 0)
-    for name in ("range1024", "range256"):
+    for name in RANGE_VARIANTS:
         _same(res["full"], res[name], name)
     p = res["range256"]
     assert p.actions()[1] == straight and p.status == fm.OK
@@ -242,16 +254,17 @@ def test_departures(fm):
     the choice equal the full sweep's."""
     sc = S.small(seed=9, n_plans=200, n_requests=6)
     t0s = [0, 15, 30, 45]
-    with _ctx(fm, sc, "full", max_slots=4) as full, _ctx(fm, sc, "range256", max_slots=4) as rq:
-        for q in range(sc.requests.n):
-            o, g = sc.requests.origin[q], sc.requests.goal[q]
-            a, ca = full.plan_departures(o, g, t0s)
-            b, cb = rq.plan_departures(o, g, t0s)
-            assert ca == cb, q
-            for x, y in zip(a, b):
-                _same(x, y, q)
-            if ca >= 0:
-                assert full.commit_plan(a[ca]) and rq.commit_plan(b[cb])
+    for name in ("range256", "auto"):                    # four per CU; one per CU on 512 threads
+        with _ctx(fm, sc, "full", max_slots=4) as full, _ctx(fm, sc, name, max_slots=4) as rq:
+            for q in range(sc.requests.n):
+                o, g = sc.requests.origin[q], sc.requests.goal[q]
+                a, ca = full.plan_departures(o, g, t0s)
+                b, cb = rq.plan_departures(o, g, t0s)
+                assert ca == cb, (name, q)
+                for x, y in zip(a, b):
+                    _same(x, y, (name, q))
+                if ca >= 0:
+                    assert full.commit_plan(a[ca]) and rq.commit_plan(b[cb])
 
 
 def test_degenerate_requests(fm):
@@ -263,23 +276,28 @@ def test_degenerate_requests(fm):
     cases = [(o, o + [5.0, -5.0, 3.0], 0), (o, o + [0.0, 0.0, 300.0], 0),
              (p0 + [20.0, 0.0, 0.0], np.array([5000.0, 5000.0, 500.0]), int(sc.plans.t0[0])),
              (np.array([-50.0, 500.0, 500.0]), np.array([5000.0, 5000.0, 500.0]), 0)]
-    with _ctx(fm, sc, "full") as full, _ctx(fm, sc, "range256") as rq:
+    with _ctx(fm, sc, "full") as full, _ctx(fm, sc, "range256") as rq, _ctx(fm, sc, "range512") as r5:
         for k, (a, g, t) in enumerate(cases):
-            x, y = full.plan_request(a, g, t), rq.plan_request(a, g, t)
+            x, y, z = full.plan_request(a, g, t), rq.plan_request(a, g, t), r5.plan_request(a, g, t)
             _log(f"[degenerate {k}] status {x.status}, {x.n_points} points")
             _same(x, y, k)
+            _same(x, z, k)
 
 
-def test_config_rejects_256_without_range_query(fm):
+@pytest.mark.parametrize("threads", [256, 512])
+def test_config_rejects_range_threads_without_range_query(fm, threads):
     cfg = S.cfg_small()
     with pytest.raises(fm.FastMDPError):
-        fm.Context(cfg, planner_threads=256)
+        fm.Context(cfg, planner_threads=threads)
     cfg.range_query, cfg.lookahead = 1, 2
     with pytest.raises(fm.FastMDPError):
-        fm.Context(cfg, planner_threads=256)
+        fm.Context(cfg, planner_threads=threads)
     cfg.lookahead = 1
-    with fm.Context(cfg, planner_threads=256) as ctx:
+    with fm.Context(cfg, planner_threads=threads) as ctx:
         assert ctx.n_plans == 0
     cfg.n_head = 65                                          # beyond the range-query planner's headings
     with pytest.raises(fm.FastMDPError):
-        fm.Context(cfg, planner_threads=256)
+        fm.Context(cfg, planner_threads=threads)
+    cfg.n_head = 24
+    with pytest.raises(fm.FastMDPError):
+        fm.Context(cfg, planner_threads=384)
