@@ -63,7 +63,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
     static_assert(4 * G4 <= 32, "a lane's candidates of a chunk fit one 32-bit mask");
     static_assert(kMaxActions % NT == 0, "actions are dealt to threads in whole rounds");
     static_assert(HMAX <= NT, "one thread per heading");
-    __shared__ __attribute__((aligned(16))) float rawX[RAW], rawY[RAW];   // the row chunk's x, y by DMA
+    // the row chunk's x, y by DMA; alone on its CU (LDS to spare) also z
+    // and visibility, so that a candidate's exact test reads no memory
+    constexpr bool ZV = NT == kRangeThreadsSolo;
+    __shared__ __attribute__((aligned(16))) float rawX[RAW], rawY[RAW];
+    __shared__ __attribute__((aligned(16))) float rawZ[ZV ? RAW : 4];
+    __shared__ __attribute__((aligned(16))) int rawV[ZV ? RAW : 4];
     __shared__ float4 tile[TILE];               // staged entries of one round; validation point list
     __shared__ double sCos[2][HMAX], sSin[2][HMAX];      // heading directions, alternate steps
     __shared__ double sStep[FASTMDP_MAX_ACT_DIM], sDz[FASTMDP_MAX_ACT_DIM];   // speed*dt, climb*dt
@@ -157,7 +162,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
     }
 
     auto row_count = [&](int row) { return (row >= 0 && row < tb.rows) ? min(tb.rowN[row], tb.cap) : 0; };
-    // Entries [base, base + min(cnt - base, RAW)) of a row: x and y travel
+    // Entries [base, base + min(cnt - base, RAW)) of a row: x and y (and z
+    // and visibility with ZV) travel
     // from the table to LDS without registers (global_load_lds), 16 bytes
     // (four entries) per lane and instruction; entry base + j lands at
     // raw*[j], in the slots of the lane that later tests it, so a wave waits
@@ -176,6 +182,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
             if (j < lim) {
                 load_lds16(tb.X + rb + j, rawX + j0);
                 load_lds16(tb.Y + rb + j, rawY + j0);
+                if constexpr (ZV) {
+                    load_lds16(tb.Z + rb + j, rawZ + j0);
+                    load_lds16(tb.vis + rb + j, rawV + j0);
+                }
             }
         }
     };
@@ -301,8 +311,15 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
                     const int jj = 4 * tid + (bit >> 2) * 4 * NT + (bit & 3);
                     const size_t idx = rb + base + jj;
                     const float xs = rawX[jj], ys = rawY[jj];   // the DMA's copy of X, Y at idx
-                    const float zs = tb.Z[idx];
-                    const int kv = tb.vis[idx];
+                    float zs;
+                    int kv;
+                    if constexpr (ZV) {
+                        zs = rawZ[jj];
+                        kv = rawV[jj];
+                    } else {
+                        zs = tb.Z[idx];
+                        kv = tb.vis[idx];
+                    }
                     const float qx = (float)((double)xs - s[0]);
                     const float qy = (float)((double)ys - s[1]);
                     const float qz = (float)((double)zs - s[2]);
