@@ -13,6 +13,7 @@ constexpr int kPlanThreads = 1024;  // planning workgroup: one request per CU, 1
 constexpr int kPropThreads = 512;   // with the proposal path: 8 wave64, twice the registers per lane
 constexpr int kRangeThreads = 256;  // range-query planner: 4 wave64, four requests per CU
 constexpr int kRangePerCU = 4;      // range-query workgroups resident per CU (LDS and registers)
+constexpr int kRangeLaunchPerCU = 2;  // FCFS requests per CU in a range-query planner launch
 constexpr int kRangeThreadsSolo = 512;  // range-query planner alone on a CU: 8 wave64, one action per thread
 constexpr int kRangeMaxHeads = 64;  // headings the range-query planner takes (its LDS budget)
 constexpr int kMaxActions = 512;
