@@ -47,12 +47,13 @@ __device__ __forceinline__ int lanes_below(uint64_t bal) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
 }
 
-// NT threads per request: kRangeThreads with kRangePerCU requests resident
-// per CU (up to 128 VGPRs each), or kRangeThreadsSolo with one per CU (no
-// register spills) for launches that hold at most one request per CU.
-template <int NT, int NC, int NV, int ZC>
+// NT threads per request: kRangeThreads with OCC requests resident per CU
+// (kRangePerCU: up to 128 VGPRs each; 2: up to 256, no register spills), or
+// kRangeThreadsSolo with one per CU (no register spills) for launches that
+// hold at most one request per CU.
+template <int NT, int OCC, int NC, int NV, int ZC>
 __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
-                          amdgpu_waves_per_eu(NT == kRangeThreads ? kRangePerCU : 2))) void range_planner_kernel(
+                          amdgpu_waves_per_eu(NT == kRangeThreads ? OCC : 2))) void range_planner_kernel(
     DevCfg cfg, DevTable tb, Slot *slots, const int *slot_list, Traj tr, int budget, int validate, int epoch,
     LaunchStop stop) {
     constexpr int NW = NT / 64;
@@ -552,11 +553,14 @@ template <int NC, int NV, int ZC>
 hipError_t launch_t(int nblk, int nt, hipStream_t st, const DevCfg &c, const DevTable &t, Slot *s, const int *list,
                     const Traj &tr, int budget, int validate, int epoch, const LaunchStop &stop) {
     if (nt == kRangeThreadsSolo)
-        hipLaunchKernelGGL((range_planner_kernel<kRangeThreadsSolo, NC, NV, ZC>), dim3(nblk), dim3(nt), 0, st, c, t,
+        hipLaunchKernelGGL((range_planner_kernel<kRangeThreadsSolo, 1, NC, NV, ZC>), dim3(nblk), dim3(nt), 0, st, c,
+                           t, s, list, tr, budget, validate, epoch, stop);
+    else if (nt == kRangeThreads && nblk <= 2 * c.n_cu)        // two per CU: no spilled registers
+        hipLaunchKernelGGL((range_planner_kernel<kRangeThreads, 2, NC, NV, ZC>), dim3(nblk), dim3(nt), 0, st, c, t,
                            s, list, tr, budget, validate, epoch, stop);
     else if (nt == kRangeThreads)
-        hipLaunchKernelGGL((range_planner_kernel<kRangeThreads, NC, NV, ZC>), dim3(nblk), dim3(nt), 0, st, c, t, s,
-                           list, tr, budget, validate, epoch, stop);
+        hipLaunchKernelGGL((range_planner_kernel<kRangeThreads, kRangePerCU, NC, NV, ZC>), dim3(nblk), dim3(nt), 0,
+                           st, c, t, s, list, tr, budget, validate, epoch, stop);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

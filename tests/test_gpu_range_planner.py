@@ -267,6 +267,25 @@ def test_departures(fm):
                     assert full.commit_plan(a[ca]) and rq.commit_plan(b[cb])
 
 
+def test_many_departures_in_one_launch(fm):
+    """640 departure rows of one request in one launch: more workgroups than
+    two per CU, so the range-query planner runs four per CU (at most 128
+    VGPRs); every candidate equals the full sweep's and the per-launch
+    choice's."""
+    sc = S.large_actions(seed=2, n_plans=3000, n_requests=1)
+    t0s = np.arange(640, dtype=np.int32)
+    o, g = sc.requests.origin[0], sc.requests.goal[0]
+    res = {}
+    for name in ("full", "range256", "auto"):
+        with _ctx(fm, sc, name, max_slots=640) as ctx:
+            res[name] = ctx.plan_departures(o, g, t0s)
+    for name in ("range256", "auto"):
+        assert res[name][1] == res["full"][1], name
+        for k, (x, y) in enumerate(zip(res["full"][0], res[name][0])):
+            _same(x, y, (name, k))
+    _log(f"[departures] chosen {res['full'][1]}")
+
+
 def test_degenerate_requests(fm):
     """Capture at the origin, a goal straight above the origin, an origin
     inside a plan's separation radius, an origin outside the box."""
