@@ -296,6 +296,7 @@ Slot fresh_slot(const fastmdp_request &r, int req_index, int seq) {
     s.status = fmdp::kRunning;
     s.req = req_index;
     s.resume_at = -1;
+    s.clean_ep = -1;
     return s;
 }
 

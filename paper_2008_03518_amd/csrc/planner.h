@@ -96,6 +96,8 @@ struct Slot {
     int cert_miss;    // proposal steps that fell back to the full sweep, accumulated
     int first;        // FCFS check: first affected point found so far (INT_MAX if none)
     int resumes;      // FCFS: times the request went back to planning, accumulated
+    int clean_ep;     // FCFS: the pass whose check found the whole trajectory consistent (-1: none since
+                      // it last finished planning)
 };
 
 // Per-slot trajectory buffers, `stride` points per slot.  seen[k] is the

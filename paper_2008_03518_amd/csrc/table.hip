@@ -250,13 +250,25 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
     const int n = S.n_points, t0 = S.t0, q = S.seq;
     const size_t base = (size_t)slot * tr.stride;
     if (tid == 0) { s_first = 0x7fffffff; s_minep = 0x7fffffff; }
-    // the oldest consistency epoch of the trajectory, and the boxes
-    int mine = 0x7fffffff;
+    // the oldest consistency epoch of the trajectory: a trajectory found
+    // consistent throughout by the last pass has every point at epoch - 2
+    if (S.clean_ep == epoch - 1) {
+        if (tid == 0) s_minep = epoch - 2;
+    } else {
+        int mine = 0x7fffffff;
+        for (int k = tid; k < n; k += kPassThreads) mine = min(mine, tr.ep[base + k]);
+        atomicMin(&s_minep, mine);
+    }
+    __syncthreads();
+    const int minep = s_minep;
+    if (minep >= epoch) return;                              // uniform: nothing withdrawn since
+    const int lo = dl.start[minep + 1], hi = dl.start[epoch];
+    if (lo + (int)blockIdx.y * kPassThreads >= hi) return;  // uniform: no logged death for this workgroup
+    // the boxes
     for (int k0 = 0; k0 < n; k0 += kPassThreads) {          // uniform
         const int k = k0 + tid;
         float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
         if (k < n) {
-            mine = min(mine, tr.ep[base + k]);
             const double *p = tr.xyz + (base + k) * 3;
             x0 = x1 = (float)p[0];
             y0 = y1 = (float)p[1];
@@ -273,11 +285,8 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_dead_kernel(DevCfg c,
             s_box[b][3] = y1;
         }
     }
-    atomicMin(&s_minep, mine);
     __syncthreads();
-    const int minep = s_minep;
-    if (minep < epoch) {
-        const int lo = dl.start[minep + 1], hi = dl.start[epoch];
+    {
         const double rs2 = c.reach_state * c.reach_state;
         const double ro2 = (c.R_sep + 1.0) * (c.R_sep + 1.0);
         const float rs = (float)c.reach_state + 1.0f, ro = (float)c.R_sep + 2.0f;
@@ -343,11 +352,15 @@ __device__ __forceinline__ void top_successor(const DevCfg &c, const Slot &S, co
 }
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_check_add_kernel(DevCfg c, DevTable tb, Slot *slots,
-                                                                      const int *list, Traj tr, PassBufs pb) {
+                                                                      const int *list, Traj tr, PassBufs pb,
+                                                                      int epoch) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = list[blockIdx.x];
     Slot &S = slots[slot];
     if (S.status == kRunning) return;                        // still planning: not in this pass
+    // checked throughout in the last pass: it saw every entry entered before
+    // this one (its rows' counts then are this pass's counts before insertion)
+    if (S.clean_ep == epoch - 1) return;
     const int n = S.n_points, t0 = S.t0, q = S.seq;
     const size_t base = (size_t)slot * tr.stride;
     const double r2 = c.reach * c.reach;
@@ -662,7 +675,10 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_finish_window_kernel(
             }
         tr.ep[base + k] = epoch - 1;
     }
-    if (tid == 0) S.resume_at = first == 0x7fffffff ? -1 : first;
+    if (tid == 0) {
+        S.resume_at = first == 0x7fffffff ? -1 : first;
+        S.clean_ep = first == 0x7fffffff ? epoch : -1;
+    }
 }
 
 // Check, part 3 (one workgroup per request): steps before the first
@@ -680,7 +696,10 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_check_finish_kernel(DevTabl
         if (row < tb.rows) tr.seen[base + k] = min(tb.rowN[row], tb.cap);
         tr.ep[base + k] = epoch - 1;
     }
-    if (tid == 0) S.resume_at = first == 0x7fffffff ? -1 : first;
+    if (tid == 0) {
+        S.resume_at = first == 0x7fffffff ? -1 : first;
+        S.clean_ep = first == 0x7fffffff ? epoch : -1;
+    }
 }
 
 __global__ __launch_bounds__(kPassThreads) void fcfs_withdraw_kernel(DevTable tb, Slot *slots, const int *list,
@@ -729,6 +748,7 @@ __global__ __launch_bounds__(kPassThreads) void fcfs_withdraw_kernel(DevTable tb
             S.status = kRunning;
             S.valid = 0;
             S.resumes += 1;
+            S.clean_ep = -1;
         }
     }
 }
@@ -847,7 +867,7 @@ hipError_t launch_fcfs_pass(const DevCfg &c, const DevTable &t, Slot *slots, con
         hipLaunchKernelGGL(fcfs_check_dead_kernel, dim3(n_list, dead_split), dim3(kPassThreads), 0, st, c, t, slots,
                            list, tr, dl, epoch);
         hipLaunchKernelGGL(fcfs_check_add_kernel, dim3(n_list, kAddSplit), dim3(kPassThreads), 0, st, c, t, slots,
-                           list, tr, pb);
+                           list, tr, pb, epoch);
         hipLaunchKernelGGL(fcfs_check_new_kernel, dim3(n_list), dim3(kPassThreads), 0, st, c, t, slots, list, tr, pb);
         hipLaunchKernelGGL(fcfs_check_finish_kernel, dim3(n_list), dim3(kPassThreads), 0, st, t, slots, list, tr,
                            epoch);
