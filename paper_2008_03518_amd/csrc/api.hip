@@ -100,6 +100,7 @@ struct fastmdp_ctx {
     size_t gather_cap = 0;                // bytes
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipEvent_t eGather = nullptr;         // after the last trajectory gather's copy to the host
+    hipStream_t gstream = nullptr;        // the gathers' stream: their copies leave the planning stream free
     // pinned staging of the engine's small per-round transfers (the copies
     // read or write it when the stream reaches them, so each region is
     // rewritten only after the round's synchronisation): gather offsets, the
@@ -166,6 +167,7 @@ void free_all(fastmdp_ctx *c) {
     if (c->eGather) hipEventDestroy(c->eGather);
     if (c->hRound) hipHostFree(c->hRound);
     if (c->own) hipStreamDestroy(c->own);
+    if (c->gstream) hipStreamDestroy(c->gstream);
 }
 
 int check_cfg(const fastmdp_config *c) {
@@ -357,11 +359,14 @@ int gather_enqueue(fastmdp_ctx *c, const std::vector<int> &slots, const std::vec
     if (m > c->max_slots) return FASTMDP_E_CAPACITY;
     std::memcpy(c->hList2, pp.slots.data(), m * sizeof(int));
     std::memcpy(c->hOff, pp.off.data(), m * sizeof(long long));
-    HIP_TRY(hipMemcpyAsync(c->dList2, c->hList2, m * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->dOff, c->hOff, m * sizeof(long long), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(fmdp::launch_gather_traj(c->dSlots, c->dList2, m, c->dOff, pp.total, c->tr, c->dGather, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->hGather, c->dGather, bytes, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipEventRecord(c->eGather, c->stream));
+    // on the gathers' own stream, so that the planning stream's next launch
+    // does not wait for the copy; the caller has synchronised the planning
+    // stream, and nothing it runs before these slots are reused writes them
+    HIP_TRY(hipMemcpyAsync(c->dList2, c->hList2, m * sizeof(int), hipMemcpyHostToDevice, c->gstream));
+    HIP_TRY(hipMemcpyAsync(c->dOff, c->hOff, m * sizeof(long long), hipMemcpyHostToDevice, c->gstream));
+    HIP_TRY(fmdp::launch_gather_traj(c->dSlots, c->dList2, m, c->dOff, pp.total, c->tr, c->dGather, c->gstream));
+    HIP_TRY(hipMemcpyAsync(c->hGather, c->dGather, bytes, hipMemcpyDeviceToHost, c->gstream));
+    HIP_TRY(hipEventRecord(c->eGather, c->gstream));
     return 0;
 }
 
@@ -460,6 +465,7 @@ int fastmdp_create(const fastmdp_config *cfg, fastmdp_ctx **out) {
     if (!rc && hipHostMalloc(reinterpret_cast<void **>(&c->hSlots), (size_t)c->max_slots * sizeof(Slot)) != hipSuccess)
         rc = FASTMDP_E_NOMEM;
     if (!rc && hipStreamCreate(&c->own) != hipSuccess) rc = FASTMDP_E_DEVICE;
+    if (!rc && hipStreamCreate(&c->gstream) != hipSuccess) rc = FASTMDP_E_DEVICE;
     if (!rc && hipEventCreate(&c->e0) != hipSuccess) rc = FASTMDP_E_DEVICE;
     if (!rc && hipEventCreate(&c->e1) != hipSuccess) rc = FASTMDP_E_DEVICE;
     if (!rc && hipEventCreateWithFlags(&c->eGather, hipEventDisableTiming) != hipSuccess) rc = FASTMDP_E_DEVICE;
@@ -828,6 +834,7 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
     int next_req = 0, next_commit = 0;
     std::vector<int> list, pass;
     PendingPlans pending;                    // accepted trajectories still being copied
+    bool gathered = false;                   // a gather was enqueued in this call
     // withdrawal log of this call: epoch e's withdrawals start at dl_start[e]
     int epoch = 0, dl_len = 0;
     std::vector<int> dl_start(2, 0);
@@ -857,7 +864,11 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
                     ++next_req;
                     dirty = true;
                 }
-            if (dirty) HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+            if (dirty) {
+                // a reused slot: its accepted trajectory's gather comes first
+                if (gathered) HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->eGather, 0));
+                HIP_TRY(hipMemcpyAsync(ctx->dSlots, hs, S * sizeof(Slot), hipMemcpyHostToDevice, ctx->stream));
+            }
             // plan the oldest running requests, one per compute unit (the
             // planner's workgroups take a CU each; the range-query planner's
             // two: it could hold four, but the oldest requests, which the later
@@ -963,11 +974,12 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
             if (!acc_slots.empty()) {
                 int rc = gather_enqueue(ctx, acc_slots, acc_reqs, hs, plans, pending);
                 if (rc) return finish(rc);
+                gathered = true;
                 for (int s : acc_slots) slot_req[s] = -1;   // reusable: the gather precedes any new planning
             }
         }
         if (!pending.empty()) {
-            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            HIP_TRY(hipEventSynchronize(ctx->eGather));
             gather_unpack(ctx, pending, plans);
         }
         return 0;
@@ -984,7 +996,7 @@ int fastmdp_plan_fcfs(fastmdp_ctx *ctx, int32_t n, const fastmdp_request *reqs, 
     // the caller are delivered; committed[] is 0 from the first unaccepted
     // request on.
     hipStreamSynchronize(ctx->stream);
-    if (!pending.empty()) gather_unpack(ctx, pending, plans);
+    if (!pending.empty() && hipEventSynchronize(ctx->eGather) == hipSuccess) gather_unpack(ctx, pending, plans);
     int m = 0;
     for (int s = 0; s < S; ++s)
         if (slot_req[s] >= 0) ctx->hPass[m++] = s;
