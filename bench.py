@@ -51,14 +51,14 @@ RANGE_ENTRY_BYTES = 8               # one row entry read by the range-query plan
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "range.hip", "planner.h", "score.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "d010c3fdf8957421e5256aa1bd1b1a814944d14fffa69d0862f698df196d1605"
+TRAFFIC_SHA256 = "9ca7bf1baff2ad5d403a6eda749ae0b2591641654ffb3149d7c0322b935bf6f7"
 # VALU counters per planner launch of an FCFS pass (profiles/planner_valu__*.md),
 # valid for the same sources: the share of SIMD cycles issuing VALU work and
 # the FLOP the hardware counts (FP32 for the sweep, FP64 for the range-query
 # planner's valuation), beside the algorithmic rooflines
-VALU_COUNTERS = {"full_sweep": {"valu_busy": 0.549, "hw_fp32_flops_per_launch": 4.65e10},
-                 "range_query": {"valu_busy": 0.166, "hw_fp64_flops_per_launch": 2.92e9}}
-TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 5.48e8, "range_query_1024": 3.61e8, "proposal": 7.19e8, "full_sweep": 3.53e8}
+VALU_COUNTERS = {"full_sweep": {"valu_busy": 0.585, "hw_fp32_flops_per_launch": 5.05e10},
+                 "range_query": {"valu_busy": 0.168, "hw_fp64_flops_per_launch": 2.92e9}}
+TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 5.19e8, "range_query_1024": 3.84e8, "proposal": 7.34e8, "full_sweep": 3.59e8}
 
 
 def _sources_match() -> bool:
