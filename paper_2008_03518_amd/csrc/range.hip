@@ -1,28 +1,31 @@
-// range.hip -- the range-query planner for gfx950: four requests per compute
-// unit, each on a 256-thread workgroup.
+// range.hip -- the range-query planner for gfx950: up to four requests per
+// compute unit on 256-thread workgroups, or one on a 512-thread workgroup.
 //
 // With the range query (Sec. VII: only the trajectories within reach of the
 // state are considered) most steps find no plan within reach, and the work
 // of a step is the FP64 valuation of every action, the argmax and the
 // advance: a chain of short phases separated by barriers and memory round
 // trips.  One request on a 1024-thread workgroup leaves the compute unit
-// idle through most of that chain; here four requests share a compute unit,
-// so that one request's waits overlap the others' work, and a step has
-// three workgroup barriers.  Per step:
+// idle through most of that chain; here two to four requests share a compute
+// unit, so that one request's waits overlap the others' work, or a request
+// alone on a compute unit runs the chain on 512 threads without spilled
+// registers; a step has three workgroup barriers.  Per step:
 //   1. x and y of the row's entries (up to 4096 per chunk) arrive in LDS by
-//      DMA while the previous step runs, and a box test against the state
+//      DMA while the previous step runs (with 512 threads z and visibility
+//      too), and a box test against the state
 //      marks candidate entries.  Its half-width exceeds the staging radius
 //      by a margin that covers every rounding of the exact test, so each
 //      entry the exact test keeps is a candidate;
 //   2. each lane takes its candidates one per round: z and visibility are
-//      read from the table and the exact test of the range query (FP64
+//      read (from the table, or from LDS) and the exact test of the range query (FP64
 //      offset from the state, FP32 squared distance against the staging
 //      radius, visible to this request) stages the same entries as the
 //      1024-thread range query, as (q_x, q_y, -2 dt q_z, |q|^2), which every
 //      thread sweeps for its actions;
 //   3. FP64 scoring, tie-band argmax and the trajectory record are those of
 //      the 1024-thread kernel (the same functions and expressions, each
-//      thread holding up to two actions), so plans, values and records are
+//      thread holding up to two actions, one with 512 threads), so plans,
+//      values and records are
 //      identical bit for bit.  Every wave publishes its candidate choice
 //      with the value, flags and nearest distance, and every thread then
 //      takes the step itself: the state lives in registers, and the heading
