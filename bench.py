@@ -51,7 +51,7 @@ RANGE_ENTRY_BYTES = 8               # one row entry read by the range-query plan
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "range.hip", "planner.h", "score.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "3228a59807d764b84b50e2b40de1ab0ee8fc4cb1cb7e09945c79451aab814b1d"
+TRAFFIC_SHA256 = "2f89d3ced56671c36fcb9cfd5f1ca8186854777b09a316d871999b0f048151a6"
 # VALU counters per planner launch of an FCFS pass (profiles/planner_valu__*.md),
 # valid for the same sources: the share of SIMD cycles issuing VALU work and
 # the FLOP the hardware counts (FP32 for the sweep, FP64 for the range-query

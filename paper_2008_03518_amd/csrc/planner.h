@@ -11,7 +11,7 @@ namespace fmdp {
 
 constexpr int kPlanThreads = 1024;  // planning workgroup: one request per CU, 16 wave64
 constexpr int kPropThreads = 512;   // with the proposal path: 8 wave64, twice the registers per lane
-constexpr int kRangeThreads = 256;  // range-query planner: 4 wave64, four requests per CU
+constexpr int kRangeThreads = 256;  // range-query planner: 4 wave64, up to four requests per CU
 constexpr int kRangePerCU = 4;      // range-query workgroups resident per CU (LDS and registers)
 constexpr int kRangeLaunchPerCU = 2;  // FCFS requests per CU in a range-query planner launch
 constexpr int kRangeThreadsSolo = 512;  // range-query planner alone on a CU: 8 wave64, one action per thread
@@ -250,7 +250,7 @@ inline bool uses_range_planner(const DevCfg &c, int prop_mode) {
 }
 // Its workgroup size for a launch of nblk requests: as configured, else
 // one request per CU on kRangeThreadsSolo threads when the launch holds no
-// more requests than CUs, four per CU on kRangeThreads otherwise.
+// more requests than CUs, two to four per CU on kRangeThreads otherwise.
 inline int range_planner_threads(const DevCfg &c, int nblk) {
     if (c.planner_threads == kRangeThreads || c.planner_threads == kRangeThreadsSolo) return c.planner_threads;
     return nblk <= c.n_cu ? kRangeThreadsSolo : kRangeThreads;
