@@ -83,12 +83,6 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
     __shared__ int s_wli[NW], s_wti[NW], s_wfl[NW];      // per wave: choice, largest, choice's flags
     __shared__ double s_wv[NW], s_wd2[NW];               // per wave: choice's value, nearest distance
     __shared__ int s_any, s_flag, s_stop;
-    // thread 0's last point taken, written once the next step's row has
-    // landed, so that its stores are not waited for with the row's loads:
-    // x, y, z, value, nearest distance; index, action, entries seen, top
-    // action, epoch, pending
-    __shared__ double st_pv[5];
-    __shared__ int st_pi[6];
     const ActTab at{sStep, sDz};
 
     const int tid = threadIdx.x;
@@ -121,7 +115,6 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
         s_any = 0;
         s_flag = 0;
         s_stop = 0;
-        st_pi[5] = 0;
     }
     // the state, the point count and the status live in every thread's
     // registers (the same values in all)
@@ -207,21 +200,28 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
     long long pairs = 0, entries = 0;
     int steps_here = 0, stop_v = 0, buf = 0;
     const float cbox = cfg.cull_box;
-    auto flush_point = [&]() {                        // thread 0
-        if (!st_pi[5]) return;
-        const size_t p = pt_base + st_pi[0];
-        tr.xyz[p * 3 + 0] = st_pv[0];
-        tr.xyz[p * 3 + 1] = st_pv[1];
-        tr.xyz[p * 3 + 2] = st_pv[2];
-        tr.val[p] = st_pv[3];
-        tr.nd[p] = st_pv[4];
-        tr.act[p] = st_pi[1];
-        tr.seen[p] = st_pi[2];
-        tr.top[p] = st_pi[3];
-        tr.ep[p] = st_pi[4];
+    // The point taken by a step is written to the trajectory during the
+    // next step's valuation, by the last wave, which scores no action in at
+    // least one round (with 360 actions or fewer) and so waits there: its
+    // coordinates are the state, its value and nearest distance stay in
+    // s_wv / s_wd2 of the winning wave until the next argmax, the rest in
+    // registers (the same in every thread).  pend: a point is not yet written.
+    int pend = 0, p_act = 0, p_seen = 0, p_top = 0, p_bw = 0;
+    auto write_point = [&]() {                        // one thread
+        const size_t p = pt_base + n - 1;
+        tr.xyz[p * 3 + 0] = s[0];
+        tr.xyz[p * 3 + 1] = s[1];
+        tr.xyz[p * 3 + 2] = s[2];
+        tr.val[p] = s_wv[p_bw];
+        tr.nd[p] = s_wd2[p_bw];
+        tr.act[p] = p_act;
+        tr.seen[p] = p_seen;
+        tr.top[p] = p_top;
+        tr.ep[p] = epoch;
         tr.col[p] = -1;
-        st_pi[5] = 0;
     };
+    // scoring rounds q that hold an action of this wave (wave-uniform)
+    const int nq = min(APT, max(0, (A - wave * 64 + NT - 1) / NT));
 
     for (;;) {
         if (status != kRunning) break;                    // uniform (registers)
@@ -267,10 +267,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
         int nn_after = 0;
         auto read_ahead = [&]() {
             nn_after = row_count(row + 2);
-            if (tid == 0) {
-                if (stop.target > 0) stop_v = __hip_atomic_load(stop.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                flush_point();
-            }
+            if (tid == 0 && stop.target > 0)
+                stop_v = __hip_atomic_load(stop.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         };
         if (n_row == 0) read_ahead();
 
@@ -385,29 +383,48 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
         //    actions whose nearest distance lies within kBand of the well
         //    radius get it recomputed exactly first.  Kept per action: value,
         //    nearest distance and whether the successor is inside a well or
-        //    below the terrain.  Both actions of a thread are scored
-        //    unconditionally (a past the last action reads the last one), so
-        //    that their FP64 chains interleave.
+        //    below the terrain.  The rounds of a wave that holds an action in
+        //    each are scored unconditionally (a past the last action reads
+        //    the last one), so that their FP64 chains interleave; a round
+        //    with no action of the wave is skipped.
         auto flags = [](const Scored &c) { return (c.I > 0.0 ? 1 : 0) | (c.clr < 0.0 ? 2 : 0); };
         double V[APT], d2v[APT];
         int fl[APT];
         bool band[APT];
         double vloc = -INFINITY;
         bool mine_band = false;
+        auto score_rounds = [&](auto nq_c) {
+            constexpr int NQ = decltype(nq_c)::value;
 #pragma unroll
-        for (int q = 0; q < APT; ++q) {
-            const int a = tid + q * NT;
-            const int ac = a < A ? a : A - 1;
-            const int h = ac / (NC * NV);
-            const double d2 = nearest_d2<NC, NV>(at, ac, mA[q]);
-            d2v[q] = d2;
-            band[q] = a < A && d2 > cfg.band_lo2 && d2 < cfg.band_hi2;
-            const Scored c = score_action(cfg, tb, at, ac, s, g, hc[h], hs[h], d2);
-            V[q] = (a < A && !band[q]) ? c.V : -INFINITY;
-            fl[q] = flags(c);
-            if (band[q]) atomicOr(&sBand[a >> 5], 1u << (a & 31));
-            mine_band = mine_band || band[q];
-            vloc = fmax(vloc, V[q]);
+            for (int q = 0; q < APT; ++q) {
+                const int a = tid + q * NT;
+                if (q >= NQ) {                            // every action of the round is past the last
+                    V[q] = -INFINITY;
+                    d2v[q] = INFINITY;
+                    fl[q] = 0;
+                    band[q] = false;
+                    continue;
+                }
+                const int ac = a < A ? a : A - 1;
+                const int h = ac / (NC * NV);
+                const double d2 = nearest_d2<NC, NV>(at, ac, mA[q]);
+                d2v[q] = d2;
+                band[q] = a < A && d2 > cfg.band_lo2 && d2 < cfg.band_hi2;
+                const Scored c = score_action(cfg, tb, at, ac, s, g, hc[h], hs[h], d2);
+                V[q] = (a < A && !band[q]) ? c.V : -INFINITY;
+                fl[q] = flags(c);
+                if (band[q]) atomicOr(&sBand[a >> 5], 1u << (a & 31));
+                mine_band = mine_band || band[q];
+                vloc = fmax(vloc, V[q]);
+            }
+        };
+        static_assert(APT <= 2, "one or two scoring rounds");
+        if (nq >= APT) score_rounds(std::integral_constant<int, APT>());
+        else if (nq == 1) score_rounds(std::integral_constant<int, 1>());
+        else score_rounds(std::integral_constant<int, 0>());
+        if (pend) {                                       // uniform
+            if (tid == NT - 64) write_point();            // the previous step's point (see above)
+            pend = 0;
         }
         double wv = wave_max(vloc);
         if (lane == 0) red_d[wave] = wv;
@@ -504,24 +521,17 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
             status = FASTMDP_NO_VALID_ACTION;
         } else {
             // every thread takes the step: the chosen action's successor (the
-            // point its scoring was computed at); thread 0 records it
+            // point its scoring was computed at), recorded as the pending point
             const int h = best / (NC * NV);
             double x, y, z;
             successor(cfg, at, best, s, hc[h], hs[h], x, y, z);
             const int flb = s_wfl[bw];
-            if (tid == 0) {
-                flush_point();                            // (a step whose row had no entries)
-                st_pv[0] = x; st_pv[1] = y; st_pv[2] = z;
-                st_pv[3] = s_wv[bw];
-                st_pv[4] = s_wd2[bw];
-                st_pi[0] = n;
-                st_pi[1] = best;
-                st_pi[2] = n_row;
-                st_pi[3] = top != best ? top : -1;
-                st_pi[4] = epoch;
-                st_pi[5] = 1;
-                pairs += (long long)A * n_vis;            // pairs with the plans this request sees
-            }
+            if (tid == 0) pairs += (long long)A * n_vis;  // pairs with the plans this request sees
+            pend = 1;
+            p_act = best;
+            p_seen = n_row;
+            p_top = top != best ? top : -1;
+            p_bw = bw;
             s[0] = x; s[1] = y; s[2] = z;
             n += 1;
             if (flb & 1) status = FASTMDP_REJECT_SEPARATION;
@@ -533,8 +543,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
         buf ^= 1;
         steps_here += 1;
     }
-    if (tid == 0) flush_point();
-    __syncthreads();   // the trajectory (thread 0's stores) complete for every thread
+    if (pend && tid == NT - 64) write_point();      // the last step's point
+    __syncthreads();   // the trajectory complete for every thread
 
     // Commit validation (shared with the 1024-thread kernel)
     if (validate && status == FASTMDP_OK) {
