@@ -288,9 +288,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT),
                 const float4 y4 = *reinterpret_cast<const float4 *>(rawY + j);
                 const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
                 const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
+                uint32_t g4 = 0u;
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
-                    if (j + m < lim && fabsf(xs[m] - sx) <= cbox && fabsf(ys[m] - sy) <= cbox) cm |= 1u << (4 * i + m);
+                    g4 |= (fmaxf(fabsf(xs[m] - sx), fabsf(ys[m] - sy)) <= cbox ? 1u : 0u) << m;
+                const int r = lim - j;                    // entries of the group inside the chunk
+                cm |= (r >= 4 ? g4 : (r > 0 ? g4 & ((1u << r) - 1u) : 0u)) << (4 * i);
             }
             // the flags of remaining candidates alternate between two
             // buffers: a buffer is rewritten only after a barrier that
