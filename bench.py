@@ -51,14 +51,14 @@ RANGE_ENTRY_BYTES = 8               # one row entry read by the range-query plan
 # WRITE_SIZE counter runs in profiles/planner_traffic__*.md (calibrated on a
 # copy of known size), valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("planner.hip", "range.hip", "planner.h", "score.h", "proposal.h", "wave.h")
-TRAFFIC_SHA256 = "f3bf9696aa7602eda1e2e02b9f0788e24182d6e40781632147e041f04478e6af"
+TRAFFIC_SHA256 = "23f389133fa73a82ee227b98009cf74962fa19b1ade96c32f7a36e31e60fd4cc"
 # VALU counters per planner launch of an FCFS pass (profiles/planner_valu__*.md),
 # valid for the same sources: the share of SIMD cycles issuing VALU work and
 # the FLOP the hardware counts (FP32 for the sweep, FP64 for the range-query
 # planner's valuation), beside the algorithmic rooflines
-VALU_COUNTERS = {"full_sweep": {"valu_busy": 0.583, "hw_fp32_flops_per_launch": 4.79e10},
-                 "range_query": {"valu_busy": 0.164, "hw_fp64_flops_per_launch": 2.21e09}}
-TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 5.26e08, "range_query_1024": 3.77e08, "proposal": 6.92e08, "full_sweep": 3.51e08}
+VALU_COUNTERS = {"full_sweep": {"valu_busy": 0.582, "hw_fp32_flops_per_launch": 4.64e10},
+                 "range_query": {"valu_busy": 0.169, "hw_fp64_flops_per_launch": 2.1e09}}
+TRAFFIC_BYTES_PER_LAUNCH = {"range_query": 5.03e08, "range_query_1024": 3.81e08, "proposal": 7.2e08, "full_sweep": 3.57e08}
 
 
 def _sources_match() -> bool:
